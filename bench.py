@@ -1,0 +1,195 @@
+"""Benchmark: weighted SART on the 256 x 720 x 128 cylindrical grid (one GPU).
+
+One step = one SART iteration: for each of the 120 views, the forward
+projection with the residual epilogue and the back-projection with the
+weighted update epilogue (all hot-path kernels), on a synthetic industrial
+part (6 coaxial annuli, 8 ring-sector inclusions, one missing), starting from
+the prior, voxel weights 1 in the inclusion ring and 0.25 elsewhere.
+
+Prints one JSON line with SART iterations/s, Grays/s (fwd+bp), the roofline
+of the dominant kernel (HIP-event kernel times) and the FP64 oracle timed on
+the host cores on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-views", type=int, default=120,
+                    help="views in the per-kernel HIP-event timing pass")
+    return ap.parse_args()
+
+
+def cpu_baseline(scan, truth, prior, weights, p, nthreads):
+    """The FP64 oracle (test infrastructure) on a bounded sample: one SART
+    sub-iteration (FP + residual + BP + update) for 2 of the 120 views,
+    scaled to SART iterations/s."""
+    from oracle import ref
+    o = ref.Oracle(scan)
+    sample_views = [0, 60]
+    t0 = time.perf_counter()
+    P = scan.det_rows * scan.det_cols
+    mu = prior.astype(np.float64).ravel().copy()
+    w = weights.astype(np.float64).ravel()
+    for k in sample_views:
+        q, L = o.fp(mu, k, k + 1, nthreads=nthreads, rowsum=True)
+        res = p[k].astype(np.float64) - q[0]
+        rho = np.where(L[0] > 0, res / np.where(L[0] > 0, L[0], 1.0), 0.0)
+        c, n = o.bp(rho, k, k + 1, nthreads=nthreads, colsum=True)
+        c, n = c.ravel(), n.ravel()
+        upd = np.where(n > 0, 0.5 * w * c / np.where(n > 0, n, 1.0), 0.0)
+        mu += upd
+    dt = time.perf_counter() - t0
+    per_view = dt / len(sample_views)
+    it_s = 1.0 / (per_view * scan.n_views)
+    return {"value": it_s, "unit": "SART it/s", "cores": nthreads, "kind": "oracle",
+            "sample": "%d of %d views (one SART sub-iteration each, %.1f s), scaled x%d"
+                      % (len(sample_views), scan.n_views, dt, scan.n_views / len(sample_views)),
+            "seconds": dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2005_11976_amd import cyl, inputs as I
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    cyl.lib()
+    tdt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[args.dtype]
+    cfg = I.config_single()
+    scan = cfg["scan"]
+    g = scan.grid
+    log("config", cfg["name"], g.shape, scan.proj_shape, "dtype", args.dtype)
+    ph = I.industrial_phantom(g, cfg["seed"])
+    G = cyl.Geometry(scan, 0)
+    truth = torch.from_numpy(ph.truth.astype(np.float32)).cuda()
+    # measured line integrals: forward projection of the truth (synthetic data)
+    p32 = G.fp(truth)
+    p = p32.to(tdt).contiguous()
+    prior = torch.from_numpy(ph.prior.astype(np.float32)).cuda().to(tdt).contiguous()
+    w = torch.from_numpy(ph.weights.astype(np.float32)).cuda().to(tdt).contiguous()
+    ws = torch.empty(G.workspace_bytes(), dtype=torch.uint8, device="cuda")
+    vol = prior.clone()
+    torch.cuda.synchronize()
+
+    log("warmup", args.warmup)
+    for _ in range(args.warmup):
+        G.sart(p, vol, 1, cfg["lam"], vox_weights=w, workspace=ws)
+    torch.cuda.synchronize()
+    vol.copy_(prior)
+    torch.cuda.synchronize()
+
+    log("timed", args.steps, "steps")
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for s in range(args.steps):
+        G.sart(p, vol, s + 1, cfg["lam"], vox_weights=w, workspace=ws, start_iter=s)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = gpu_ms / args.steps
+    it_s = 1000.0 / ms_per_step
+    rays = scan.n_views * scan.det_rows * scan.det_cols
+    grays = 2.0 * rays * it_s / 1e9
+    log("SART %.3f it/s  %.2f ms/iter  %.3f Grays/s (wall %.2f s)" % (it_s, ms_per_step, grays, wall))
+
+    # reconstruction quality vs the truth (reported, not a parity claim)
+    rel_truth = float((vol.float() - truth).norm() / truth.norm())
+
+    # per-kernel HIP-event timing on the launch stream
+    nk = min(args.kernel_views, scan.n_views)
+    log("kernel timing over", nk, "views")
+    vol2 = prior.clone()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(3 * nk)]
+    for i in range(nk):
+        evs[3 * i].record()
+        G.sart_residual(i, p, vol2, ws)
+        evs[3 * i + 1].record()
+        G.sart_update(i, vol2, ws, cfg["lam"], vox_weights=w)
+        evs[3 * i + 2].record()
+    torch.cuda.synchronize()
+    fp_ms = float(np.mean([evs[3 * i].elapsed_time(evs[3 * i + 1]) for i in range(nk)]))
+    bp_ms = float(np.mean([evs[3 * i + 1].elapsed_time(evs[3 * i + 2]) for i in range(nk)]))
+    log("kernel avg ms: fp_residual %.4f  bp_update %.4f" % (fp_ms, bp_ms))
+
+    s_mu = {"f32": 4, "f16": 2, "bf16": 2}[args.dtype]
+    V = g.n_vox
+    P = scan.det_rows * scan.det_cols
+    # algorithmic bytes per launch (one view): FP reads mu and p, writes rho;
+    # BP reads rho, reads mu and w, writes mu
+    fp_bytes = V * s_mu + P * (s_mu + 4)
+    bp_bytes = P * 4 + V * (2 * s_mu + s_mu)
+    dom = "bp_update" if bp_ms >= fp_ms else "fp_residual"
+    dom_bytes = bp_bytes if dom == "bp_update" else fp_bytes
+    dom_ms = max(bp_ms, fp_ms)
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    iter_bytes = scan.n_views * (fp_bytes + bp_bytes)
+    path_gbs = iter_bytes * it_s / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        nthreads = max(1, min(16, len(os.sched_getaffinity(0))))
+        log("cpu baseline (oracle) on", nthreads, "threads")
+        cpu = cpu_baseline(scan, ph.truth, ph.prior, ph.weights, p32.cpu().numpy(), nthreads)
+        log("cpu baseline %.5f it/s" % cpu["value"])
+
+    out = {
+        "metric": "SART iters/s (weighted, from prior) at 256x720x128, 120 views of 512x512",
+        "value": it_s,
+        "unit": "SART it/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "grid": list(g.shape), "views": scan.n_views,
+                   "detector": [scan.det_rows, scan.det_cols], "iterations_per_step": 1,
+                   "lambda": cfg["lam"], "weighted": True, "prior": True},
+        "grays_per_s_fwd_bp": grays,
+        "path_hbm_gbs_algorithmic": path_gbs,
+        "path_hbm_frac": path_gbs / HBM_PEAK_GBS,
+        "kernel_ms": {"fp_residual": fp_ms, "bp_update": bp_ms},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": dom_bytes},
+        "cpu_baseline": cpu,
+        "rel_err_vs_truth": rel_truth,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/*
+ * cyl.h — C ABI of libcyl: cone-beam forward projection, its exact transpose
+ * and weighted SART on an object-fixed cylindrical voxel grid, on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Paper: "Fast tomographic inspection of cylindrical objects" (arXiv 2005.11976).
+ *   Sec. 2, Eq. 1    object pose  X' = R X + T  (stage frame X -> object frame X')
+ *   Sec. 2, Eq. 2    cylindrical cells:  r = sqrt(x'^2 + y'^2), theta = atan2(y', x'),
+ *                    h = z'  (the printed arctan(y'/x') is read as the two-argument
+ *                    arctangent taken modulo 2 pi)
+ *   Sec. 2.2, Eq. 6  p_j = sum_l t_jl mu_l, t_jl = length of ray j inside cell l
+ *   Sec. 2.2, Eq. 7  SART update per projection with relaxation lambda, row sums
+ *                    sum_l t_jl and column sums sum_j t_jm
+ *   Sec. 2.2, last paragraph: voxel weight map (weighted back-projection);
+ *   Sec. 1 and 3.3:  prior (initial) volume.
+ *
+ * Conventions shared by every entry point
+ *   - lengths in mm, angles in radians, attenuation in 1/mm;
+ *   - grid: r_i = r_min + i (r_max - r_min)/n_r, h_m = h_min + m (h_max - h_min)/n_h,
+ *     theta_b = theta0 + 2 pi b / n_theta; every cell is half-open [lower, upper);
+ *   - volumes are C-ordered [n_h][n_theta][n_r] (r fastest);
+ *   - projections are C-ordered [n_views][det_rows][det_cols];
+ *   - ray j = (view k, row v, col u) runs from the source S_k to the pixel centre
+ *     D_k + (u - (det_cols-1)/2) U_k + (v - (det_rows-1)/2) V_k (one ray per pixel);
+ *   - every array argument except cyl_traj.views and cyl_sart_params.view_order is
+ *     a DEVICE pointer owned by the caller (e.g. the storage of a contiguous torch
+ *     tensor on the geometry's device); the library never frees caller memory;
+ *   - calls validate their arguments, enqueue work on `hip_stream` (a hipStream_t,
+ *     NULL = the default stream) and return before the work completes.  A failed
+ *     validation returns CYL_EINVAL, enqueues nothing and sets cyl_last_error().
+ *     A launch failure returns CYL_EDEVICE.  Faults inside kernels surface at the
+ *     caller's next synchronisation of the stream;
+ *   - a cyl_geom is immutable after creation, so several streams and threads may
+ *     share it; calls that write the same buffer must be ordered by the caller.
+ */
+#ifndef CYL_H
+#define CYL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cyl_geom cyl_geom; /* opaque */
+
+/* Storage types of volumes, projections and weights.  Arithmetic is always
+ * FP32 (FP64 for the per-ray set-up and the row sums); FP16/BF16 values are
+ * widened on load and rounded to nearest-even on store. */
+typedef enum { CYL_F32 = 0, CYL_F16 = 1, CYL_BF16 = 2 } cyl_dtype;
+
+enum {
+    CYL_OK = 0,
+    CYL_EINVAL = -1,      /* invalid argument; nothing enqueued */
+    CYL_ENOMEM = -2,      /* device allocation failed */
+    CYL_EDEVICE = -3,     /* HIP runtime or launch error */
+    CYL_EUNSUPPORTED = -4 /* valid but not supported by this build */
+};
+
+/* Cylindrical grid in the object frame (Sec. 2, Eq. 2).
+ * Requires n_h, n_theta, n_r >= 1, 0 <= r_min < r_max, h_min < h_max. */
+typedef struct {
+    int32_t n_h, n_theta, n_r;
+    double r_min, r_max;
+    double h_min, h_max;
+    double theta0; /* lower edge of sector 0 */
+} cyl_grid;
+
+/* Source/detector trajectory (Sec. 2.1 and Table 1: circular or any other
+ * trajectory; Sec. 1 mentions conveyor belts).  One 12-vector per view in the
+ * STAGE frame: source[3], detector centre[3], pixel step along a row (u)[3],
+ * pixel step along a column (v)[3].  `views` is a HOST pointer, read during
+ * cyl_geom_create only.  Requires n_views, det_rows, det_cols >= 1 and a
+ * non-degenerate detector (u and v steps not parallel, source off the
+ * detector plane). */
+typedef struct {
+    int32_t n_views, det_rows, det_cols;
+    const double *views;
+} cyl_traj;
+
+/* Rigid pose of the object (Sec. 2, Eq. 1): X' = R X + T, R row-major.  R must
+ * be a rotation (orthonormal to 1e-9, det +1). */
+typedef struct {
+    double R[9];
+    double T[3];
+} cyl_pose;
+
+/* Builds the immutable geometry on HIP device `device`: validates the inputs,
+ * maps every view into the object frame in FP64 (Eq. 1 applied once per view,
+ * the paper's precomputed alignment, Sec. 2.2) and uploads the grid tables.
+ * Fails with CYL_EINVAL if any source point lies inside the grid support
+ * (r < r_max and h_min <= h < h_max in the object frame).  Device memory owned
+ * by the geometry: a few hundred bytes per view plus the grid tables; freed by
+ * cyl_geom_destroy.  *out is set only on success. */
+int cyl_geom_create(const cyl_grid *grid, const cyl_traj *traj, const cyl_pose *pose,
+                    int device, cyl_geom **out);
+
+/* Frees the geometry (NULL is ignored).  The caller must make sure no enqueued
+ * work still uses it. */
+void cyl_geom_destroy(cyl_geom *geom);
+
+/* Forward projection (Eq. 6): proj[k][v][u] = sum_l t_jl vol_l for the views
+ * k in [view_begin, view_end).  `vol` is the full volume; `proj` is the full
+ * [n_views][rows][cols] array of which only those views are written.  t_jl is
+ * the exact length of the source -> pixel-centre segment inside cell l,
+ * accumulated in FP32 along the ray.  An empty range is a no-op. */
+int cyl_fp(const cyl_geom *geom, const void *vol, cyl_dtype vol_type, void *proj,
+           cyl_dtype proj_type, int32_t view_begin, int32_t view_end, void *hip_stream);
+
+/* Back-projection, the exact transpose of cyl_fp:
+ * vol_l = (accumulate ? vol_l : 0) + sum_{k in range} sum_j t_jl proj_j.
+ * No normalisation.  `proj` is the full [n_views][rows][cols] array of which
+ * only the views in range are read.  Deterministic: no global atomics; every
+ * voxel is written once by the wave that owns it. */
+int cyl_bp(const cyl_geom *geom, const void *proj, cyl_dtype proj_type, void *vol,
+           cyl_dtype vol_type, int32_t view_begin, int32_t view_end, int32_t accumulate,
+           void *hip_stream);
+
+/* Row sums L_j = sum_l t_jl (Eq. 7 denominator) in closed form: the length of
+ * the ray inside the support r_min <= r < r_max, h_min <= h < h_max, computed
+ * in FP64 per ray and stored as FP32 into the full [n_views][rows][cols]
+ * array `out` for the views in range. */
+int cyl_row_sums(const cyl_geom *geom, float *out, int32_t view_begin, int32_t view_end,
+                 void *hip_stream);
+
+/* SART parameters (Eq. 7).  One update step per projection (the ordered subset
+ * is one view); one iteration sweeps all views in `view_order` (HOST pointer to
+ * n_views indices, each in [0, n_views); NULL = 0 .. n_views-1).  Resume: start
+ * at iteration start_iter, position start_view of the order (0, 0 = fresh).
+ * nonneg != 0 clamps mu at 0 after every update. */
+typedef struct {
+    int32_t n_iter;
+    double lambda;
+    int32_t nonneg;
+    const int32_t *view_order;
+    int32_t start_iter, start_view;
+} cyl_sart_params;
+
+/* Device workspace bytes cyl_sart_run needs for this geometry. */
+size_t cyl_sart_workspace_bytes(const cyl_geom *geom, const cyl_sart_params *params);
+
+/* Weighted SART from a prior (Eq. 7; weight map Sec. 2.2; prior Sec. 1, 3.3).
+ * For each iteration and each view k in order:
+ *   q_j   = sum_l t_jl mu_l                          (FP32 along the ray)
+ *   rho_j = wp_j (p_j - q_j) / L_j   if L_j > 0 else 0   (L_j: closed-form row sum)
+ *   c_m   = sum_{j in k} t_jm rho_j,  n_m = sum_{j in k} t_jm
+ *   mu_m += lambda * wv_m * c_m / n_m   if n_m > 0    (rounded into vol_type)
+ * proj: measured line integrals p (Eq. 6), [n_views][rows][cols].
+ * proj_weights: per-pixel weights wp, same layout, or NULL (all 1).
+ * vox_weights: per-voxel weights wv (volume layout), or NULL (all 1).
+ * vol: in = prior mu(0), out = result, updated in place.
+ * workspace: device buffer of at least cyl_sart_workspace_bytes() bytes, owned
+ * by the caller, not used by anything else until the work completes. */
+int cyl_sart_run(const cyl_geom *geom, const cyl_sart_params *params, const void *proj,
+                 cyl_dtype proj_type, const void *proj_weights, cyl_dtype proj_weights_type,
+                 const void *vox_weights, cyl_dtype vox_weights_type, void *vol,
+                 cyl_dtype vol_type, void *workspace, size_t workspace_bytes,
+                 void *hip_stream);
+
+/* The two kernels of one SART sub-iteration (Eq. 7, one view), for callers
+ * that schedule views themselves (a serving loop interleaving scans, or a
+ * profiler timing each kernel).  Running, for k in order,
+ * cyl_sart_residual(k) then cyl_sart_update(k) on one stream is exactly
+ * cyl_sart_run.
+ * cyl_sart_residual: rho_j = wp_j (p_j - sum_l t_jl mu_l) / L_j for the rays of
+ *   view `view`, written as FP32 into `workspace` ([rows][cols]).
+ * cyl_sart_update: c_m = sum_j t_jm rho_j, n_m = sum_j t_jm over that view's
+ *   rays; mu_m += lambda wv_m c_m / n_m where n_m > 0 (clamped at 0 if nonneg).
+ * Arguments as for cyl_sart_run; workspace of cyl_sart_workspace_bytes(). */
+int cyl_sart_residual(const cyl_geom *geom, int32_t view, const void *proj, cyl_dtype proj_type,
+                      const void *proj_weights, cyl_dtype proj_weights_type, const void *vol,
+                      cyl_dtype vol_type, void *workspace, size_t workspace_bytes, void *hip_stream);
+int cyl_sart_update(const cyl_geom *geom, int32_t view, double lambda, int32_t nonneg,
+                    const void *vox_weights, cyl_dtype vox_weights_type, void *vol, cyl_dtype vol_type,
+                    const void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *cyl_last_error(void);
+
+/* Library version string. */
+const char *cyl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CYL_H */

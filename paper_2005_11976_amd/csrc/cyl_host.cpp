@@ -1,0 +1,291 @@
+// Host side of libcyl: argument validation, FP64 geometry precompute (Eq. 1
+// applied once per view), grid tables, error reporting.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "cyl_internal.h"
+
+namespace cyl {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int check_dtype(cyl_dtype t, const char *what) {
+    if (t != CYL_F32 && t != CYL_F16 && t != CYL_BF16) {
+        set_error("%s: unsupported dtype %d", what, (int)t);
+        return CYL_EINVAL;
+    }
+    return CYL_OK;
+}
+
+size_t dtype_size(cyl_dtype t) { return t == CYL_F32 ? 4 : 2; }
+
+static bool finite3(const double *v) {
+    return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+static void mat_vec(const double R[9], const double x[3], double out[3]) {
+    for (int i = 0; i < 3; ++i) out[i] = R[3 * i] * x[0] + R[3 * i + 1] * x[1] + R[3 * i + 2] * x[2];
+}
+
+// Inverse of the 3x3 matrix with columns c0, c1, c2; false if singular.
+static bool inverse_cols(const double c0[3], const double c1[3], const double c2[3], double inv[9]) {
+    double m[9] = {c0[0], c1[0], c2[0], c0[1], c1[1], c2[1], c0[2], c1[2], c2[2]};
+    double det = m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+                 m[2] * (m[3] * m[7] - m[4] * m[6]);
+    double scale = 1.0;
+    for (int i = 0; i < 3; ++i) scale *= std::sqrt(c0[i] * c0[i] + c1[i] * c1[i] + c2[i] * c2[i]) + 1e-300;
+    if (!(std::fabs(det) > 1e-12 * scale)) return false;
+    double id = 1.0 / det;
+    inv[0] = (m[4] * m[8] - m[5] * m[7]) * id;
+    inv[1] = (m[2] * m[7] - m[1] * m[8]) * id;
+    inv[2] = (m[1] * m[5] - m[2] * m[4]) * id;
+    inv[3] = (m[5] * m[6] - m[3] * m[8]) * id;
+    inv[4] = (m[0] * m[8] - m[2] * m[6]) * id;
+    inv[5] = (m[2] * m[3] - m[0] * m[5]) * id;
+    inv[6] = (m[3] * m[7] - m[4] * m[6]) * id;
+    inv[7] = (m[1] * m[6] - m[0] * m[7]) * id;
+    inv[8] = (m[0] * m[4] - m[1] * m[3]) * id;
+    return true;
+}
+
+static float2 split(double x) {
+    float hi = (float)x;
+    float lo = (float)(x - (double)hi);
+    return make_float2(hi, lo);
+}
+
+}  // namespace cyl
+
+using namespace cyl;
+
+extern "C" const char *cyl_last_error(void) { return g_err; }
+
+extern "C" const char *cyl_version(void) { return "libcyl 0.1 (gfx950)"; }
+
+extern "C" int cyl_geom_create(const cyl_grid *grid, const cyl_traj *traj, const cyl_pose *pose,
+                               int device, cyl_geom **out) {
+    if (!grid || !traj || !pose || !out) {
+        set_error("cyl_geom_create: NULL argument");
+        return CYL_EINVAL;
+    }
+    const cyl_grid g = *grid;
+    if (g.n_h < 1 || g.n_theta < 1 || g.n_r < 1) {
+        set_error("cyl_geom_create: grid sizes must be >= 1 (got %d x %d x %d)", g.n_h, g.n_theta, g.n_r);
+        return CYL_EINVAL;
+    }
+    if ((int64_t)g.n_h * g.n_theta * g.n_r > (int64_t)INT32_MAX) {
+        set_error("cyl_geom_create: grid has more than 2^31-1 cells");
+        return CYL_EINVAL;
+    }
+    if (!(std::isfinite(g.r_min) && std::isfinite(g.r_max) && std::isfinite(g.h_min) &&
+          std::isfinite(g.h_max) && std::isfinite(g.theta0))) {
+        set_error("cyl_geom_create: non-finite grid extent");
+        return CYL_EINVAL;
+    }
+    if (!(g.r_min >= 0.0 && g.r_min < g.r_max)) {
+        set_error("cyl_geom_create: need 0 <= r_min < r_max (got %g, %g)", g.r_min, g.r_max);
+        return CYL_EINVAL;
+    }
+    if (!(g.h_min < g.h_max)) {
+        set_error("cyl_geom_create: need h_min < h_max (got %g, %g)", g.h_min, g.h_max);
+        return CYL_EINVAL;
+    }
+    if (traj->n_views < 1 || traj->det_rows < 1 || traj->det_cols < 1 || !traj->views) {
+        set_error("cyl_geom_create: trajectory needs n_views, det_rows, det_cols >= 1 and views");
+        return CYL_EINVAL;
+    }
+    if ((int64_t)traj->det_rows * traj->det_cols > (int64_t)1 << 28) {
+        set_error("cyl_geom_create: detector larger than 2^28 pixels");
+        return CYL_EINVAL;
+    }
+    // pose must be a rotation
+    const double *R = pose->R;
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(R[i])) {
+            set_error("cyl_geom_create: non-finite rotation");
+            return CYL_EINVAL;
+        }
+    if (!finite3(pose->T)) {
+        set_error("cyl_geom_create: non-finite translation");
+        return CYL_EINVAL;
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double dot = R[3 * i] * R[3 * j] + R[3 * i + 1] * R[3 * j + 1] + R[3 * i + 2] * R[3 * j + 2];
+            if (std::fabs(dot - (i == j ? 1.0 : 0.0)) > 1e-9) {
+                set_error("cyl_geom_create: R is not orthonormal");
+                return CYL_EINVAL;
+            }
+        }
+    double det = R[0] * (R[4] * R[8] - R[5] * R[7]) - R[1] * (R[3] * R[8] - R[5] * R[6]) +
+                 R[2] * (R[3] * R[7] - R[4] * R[6]);
+    if (det < 0.0) {
+        set_error("cyl_geom_create: R is a reflection (det < 0)");
+        return CYL_EINVAL;
+    }
+    int ndev = 0;
+    // per-view object-frame geometry (Eq. 1, FP64)
+    const int nv = traj->n_views, H = traj->det_rows, W = traj->det_cols;
+    std::vector<ViewDev> views(nv);
+    const double cu = 0.5 * (W - 1), cv = 0.5 * (H - 1);
+    for (int k = 0; k < nv; ++k) {
+        const double *w = traj->views + 12 * (size_t)k;
+        for (int i = 0; i < 12; ++i)
+            if (!std::isfinite(w[i])) {
+                set_error("cyl_geom_create: view %d has a non-finite entry", k);
+                return CYL_EINVAL;
+            }
+        double S[3], D[3], U[3], V[3];
+        mat_vec(R, w, S);
+        mat_vec(R, w + 3, D);
+        mat_vec(R, w + 6, U);
+        mat_vec(R, w + 9, V);
+        for (int i = 0; i < 3; ++i) {
+            S[i] += pose->T[i];
+            D[i] += pose->T[i];
+        }
+        ViewDev &vd = views[k];
+        for (int i = 0; i < 3; ++i) {
+            vd.a[i] = S[i];
+            vd.U[i] = U[i];
+            vd.V[i] = V[i];
+            vd.d0[i] = D[i] - cu * U[i] - cv * V[i] - S[i];
+            vd.af[i] = (float)S[i];
+        }
+        // source must be outside the grid support
+        double rs = std::hypot(S[0], S[1]);
+        if (rs < g.r_max && S[2] >= g.h_min && S[2] < g.h_max) {
+            set_error("cyl_geom_create: source of view %d lies inside the grid support", k);
+            return CYL_EINVAL;
+        }
+        double Qi[9];
+        if (!inverse_cols(vd.d0, vd.U, vd.V, Qi)) {
+            set_error("cyl_geom_create: view %d has a degenerate detector", k);
+            return CYL_EINVAL;
+        }
+        for (int i = 0; i < 9; ++i) vd.Qi[i] = (float)Qi[i];
+    }
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) {
+        set_error("cyl_geom_create: no HIP device (%s)", hipGetErrorString(e));
+        return CYL_EDEVICE;
+    }
+    if (device < 0 || device >= ndev) {
+        set_error("cyl_geom_create: device %d out of range [0, %d)", device, ndev);
+        return CYL_EINVAL;
+    }
+    int prev = 0;
+    hipGetDevice(&prev);
+    if ((e = hipSetDevice(device)) != hipSuccess) {
+        set_error("cyl_geom_create: hipSetDevice(%d): %s", device, hipGetErrorString(e));
+        return CYL_EDEVICE;
+    }
+    // grid tables
+    std::vector<float2> rt(g.n_r + 1), ht(g.n_h + 1), cs(g.n_theta + 1);
+    std::vector<double2> cs64(g.n_theta + 1);
+    const double dr = (g.r_max - g.r_min) / g.n_r, dh = (g.h_max - g.h_min) / g.n_h;
+    const double dth = 2.0 * M_PI / g.n_theta;
+    for (int i = 0; i <= g.n_r; ++i) rt[i] = split(g.r_min + i * dr);
+    for (int m = 0; m <= g.n_h; ++m) ht[m] = split(g.h_min + m * dh);
+    for (int b = 0; b <= g.n_theta; ++b) {
+        double th = g.theta0 + b * dth;
+        cs64[b] = make_double2(std::cos(th), std::sin(th));
+        cs[b] = make_float2((float)cs64[b].x, (float)cs64[b].y);
+    }
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t off_views = 0;
+    size_t off_r = align(off_views + sizeof(ViewDev) * nv);
+    size_t off_h = align(off_r + sizeof(float2) * rt.size());
+    size_t off_cs = align(off_h + sizeof(float2) * ht.size());
+    size_t off_cs64 = align(off_cs + sizeof(float2) * cs.size());
+    size_t total = align(off_cs64 + sizeof(double2) * cs64.size());
+    void *dmem = nullptr;
+    if ((e = hipMalloc(&dmem, total)) != hipSuccess) {
+        hipSetDevice(prev);
+        set_error("cyl_geom_create: hipMalloc(%zu): %s", total, hipGetErrorString(e));
+        return CYL_ENOMEM;
+    }
+    char *base = (char *)dmem;
+    bool ok = hipMemcpy(base + off_views, views.data(), sizeof(ViewDev) * nv, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(base + off_r, rt.data(), sizeof(float2) * rt.size(), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(base + off_h, ht.data(), sizeof(float2) * ht.size(), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(base + off_cs, cs.data(), sizeof(float2) * cs.size(), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(base + off_cs64, cs64.data(), sizeof(double2) * cs64.size(), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        hipFree(dmem);
+        hipSetDevice(prev);
+        set_error("cyl_geom_create: upload of the geometry tables failed");
+        return CYL_EDEVICE;
+    }
+    cyl_geom *G = new (std::nothrow) cyl_geom;
+    if (!G) {
+        hipFree(dmem);
+        hipSetDevice(prev);
+        set_error("cyl_geom_create: out of host memory");
+        return CYL_ENOMEM;
+    }
+    G->device = device;
+    G->grid = g;
+    G->n_views = nv;
+    G->rows = H;
+    G->cols = W;
+    G->dmem = dmem;
+    GeomDev &d = G->dev;
+    d.n_h = g.n_h;
+    d.n_theta = g.n_theta;
+    d.n_r = g.n_r;
+    d.n_views = nv;
+    d.rows = H;
+    d.cols = W;
+    d.r_min = (float)g.r_min;
+    d.dr = (float)dr;
+    d.h_min = (float)g.h_min;
+    d.dh = (float)dh;
+    d.theta0 = (float)g.theta0;
+    d.dtheta = (float)dth;
+    d.r_min_d = g.r_min;
+    d.r_max_d = g.r_max;
+    d.h_min_d = g.h_min;
+    d.h_max_d = g.h_max;
+    d.views = (const ViewDev *)(base + off_views);
+    d.r_tab = (const float2 *)(base + off_r);
+    d.h_tab = (const float2 *)(base + off_h);
+    d.cs_tab = (const float2 *)(base + off_cs);
+    d.cs64 = (const double2 *)(base + off_cs64);
+    // back-projection blocks: flat in h, wide in theta and r; wedges no wider than pi
+    d.bh = g.n_h < 4 ? g.n_h : 4;
+    d.br = g.n_r < 16 ? g.n_r : 16;
+    int bt = g.n_theta / 2;
+    if (bt < 1) bt = 1;
+    if (bt > 16) bt = 16;
+    d.bt = bt;
+    d.nbh = (g.n_h + d.bh - 1) / d.bh;
+    d.nbt = (g.n_theta + d.bt - 1) / d.bt;
+    d.nbr = (g.n_r + d.br - 1) / d.br;
+    hipSetDevice(prev);
+    *out = G;
+    return CYL_OK;
+}
+
+extern "C" void cyl_geom_destroy(cyl_geom *geom) {
+    if (!geom) return;
+    int prev = 0;
+    hipGetDevice(&prev);
+    hipSetDevice(geom->device);
+    hipFree(geom->dmem);
+    hipSetDevice(prev);
+    delete geom;
+}

@@ -1,0 +1,986 @@
+// HIP kernels of libcyl (gfx950): cylindrical Siddon traversal, forward
+// projection with the SART residual epilogue, block-owned back-projection
+// with the SART update epilogue, closed-form row sums, and the C entry points
+// that launch them.
+//
+// Ray model (Sec. 2.2, Eq. 6): one ray per pixel from the source to the pixel
+// centre; t_jl is the exact length of that segment inside ring-sector cell l
+// (Sec. 2, Eq. 2).  The traversal parametrises each ray by its arc length s
+// (mm) measured from the point of closest approach to the object axis, so all
+// FP32 crossing parameters stay small and well conditioned:
+//   r-shells      r(s)^2 = b^2 + (kappa s)^2         ->  s = +-sqrt((r-b)(r+b)) / kappa
+//   sector edges  n_b . (c + s e_xy) = 0             ->  s = -(n_b . c) / (n_b . e_xy)
+//   axial planes  z(s) = z_c + s e_z                 ->  s = (h_m - z_c) / e_z
+// b, c and z_c come from an FP64 set-up per ray; b and the table radii carry a
+// second FP32 word so r - b keeps its precision at grazing incidence.
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "cyl_internal.h"
+
+namespace cyl {
+
+#define CYL_INF __builtin_huge_valf()
+
+// ------------------------------------------------------------ storage types
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t x) { return __uint_as_float((uint32_t)x << 16); }
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                                             // nearest even
+    return (uint16_t)(u >> 16);
+}
+
+template <int DT>
+struct Store;
+template <>
+struct Store<CYL_F32> {
+    static __device__ __forceinline__ float ld(const void *p, size_t i) { return ((const float *)p)[i]; }
+    static __device__ __forceinline__ void st(void *p, size_t i, float v) { ((float *)p)[i] = v; }
+};
+template <>
+struct Store<CYL_F16> {
+    static __device__ __forceinline__ float ld(const void *p, size_t i) {
+        return __half2float(((const __half *)p)[i]);
+    }
+    static __device__ __forceinline__ void st(void *p, size_t i, float v) {
+        ((__half *)p)[i] = __float2half_rn(v);
+    }
+};
+template <>
+struct Store<CYL_BF16> {
+    static __device__ __forceinline__ float ld(const void *p, size_t i) {
+        return bf16_to_f32(((const uint16_t *)p)[i]);
+    }
+    static __device__ __forceinline__ void st(void *p, size_t i, float v) {
+        ((uint16_t *)p)[i] = f32_to_bf16(v);
+    }
+};
+
+// Load of a runtime-typed optional array (weights); the switch is uniform.
+__device__ __forceinline__ float ld_any(const void *p, int dt, size_t i) {
+    if (dt == CYL_F32) return Store<CYL_F32>::ld(p, i);
+    if (dt == CYL_F16) return Store<CYL_F16>::ld(p, i);
+    return Store<CYL_BF16>::ld(p, i);
+}
+
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// ------------------------------------------------------------ per-ray set-up
+
+enum : int { RAY_HIT = 1, RAY_AXIAL = 2, RAY_THRU = 4 };
+
+struct RayF {
+    float cx, cy;      // closest point to the axis (xy), s = 0
+    float ex, ey, ez;  // unit direction
+    float zc, zclo;    // z at s = 0 as hi + lo (shallow rays amplify its rounding)
+    float inv_ez;      // 1 / e_z
+    float b, blo;      // closest-approach distance as hi + lo
+    float inv_k;       // |d| / |d_xy|
+    float s_in, s_out; // parameter interval inside the grid support
+    int flags;
+    int it_in, it_out; // sectors before / after the axis for rays through it
+    float len;         // |d|
+    double dxd, dyd;   // xy of the FP64 direction d (source -> pixel centre)
+    double tcd;        // FP64 closest-approach parameter (s = (t - tc) |d|)
+};
+
+// Sector containing the direction (x, y).
+__device__ __forceinline__ int sector_of(const GeomDev &g, float x, float y) {
+    if (g.n_theta == 1) return 0;
+    const float two_pi = 6.28318530717958647692f;
+    float th = atan2f(y, x) - g.theta0;
+    th -= two_pi * floorf(th * (1.0f / two_pi));
+    int it = (int)floorf(th / g.dtheta);
+    it = it < 0 ? 0 : it;
+    return it >= g.n_theta ? g.n_theta - 1 : it;
+}
+
+// Parameter where the ray meets shell radius rt (hi, lo): the magnitude
+// sqrt((r - b)(r + b)) / kappa, or -1 if the ray passes outside the shell.
+__device__ __forceinline__ float shell_w(float2 rt, const RayF &r) {
+    float diff = (rt.x - r.b) + (rt.y - r.blo);
+    if (!(diff > 0.0f)) return -1.0f;
+    return fsqrt(diff * (rt.x + r.b)) * r.inv_k;
+}
+
+// Parameter where the ray meets the axial plane ht (hi, lo).
+__device__ __forceinline__ float plane_s(float2 ht, const RayF &r) {
+    return ((ht.x - r.zc) + (ht.y - r.zclo)) * r.inv_ez;
+}
+
+// Crossing of the ray with the full line through the axis along sector edge
+// b.  s: the parameter; ne, nc: n.e_xy and n.c with n = (-sin, cos) of the
+// edge (their signs give the side of the line, for half-plane tests);
+// on_edge: the meeting is on the edge's half-line (the ray sweeps less than
+// pi, so the edge direction must lie within 90 degrees of the closest point c).
+// When the ray runs nearly parallel to the edge line (|n.e| < kEdgeTau, only
+// rays passing close to the axis), the FP32 quotient is ill-conditioned and the
+// crossing is solved in FP64 on the unrounded ray.
+constexpr float kEdgeTau = 0.0625f;
+
+struct EdgeX {
+    float s, ne, nc;
+    bool on_edge;
+};
+
+__device__ __forceinline__ EdgeX edge_cross(const GeomDev &g, const ViewDev &V, const RayF &r, int b) {
+    EdgeX x;
+    const float2 cs = g.cs_tab[b];
+    x.nc = cs.x * r.cy - cs.y * r.cx;
+    x.ne = cs.x * r.ey - cs.y * r.ex;
+    if (fabsf(x.ne) >= kEdgeTau) {
+        x.on_edge = (cs.x * r.cx + cs.y * r.cy) > 0.0f;
+        x.s = -x.nc * frcp(x.ne);
+        return x;
+    }
+    const double2 c = g.cs64[b];
+    const double nd = c.x * r.dyd - c.y * r.dxd;
+    const double na = c.x * V.a[1] - c.y * V.a[0];
+    x.ne = (float)nd;
+    x.nc = (float)na;
+    if (nd == 0.0) {
+        x.on_edge = false;
+        x.s = CYL_INF;
+        return x;
+    }
+    const double t = -na / nd;
+    const double px = fma(t, r.dxd, V.a[0]), py = fma(t, r.dyd, V.a[1]);
+    x.on_edge = (c.x * px + c.y * py) > 0.0;
+    x.s = (float)((t - r.tcd) * (double)r.len);
+    return x;
+}
+
+// Cheap mostly-FP32 ray set-up shared by every kernel.  FP64 is used for the
+// pixel direction, the closest-approach parameter (one FP64 Newton step on an
+// FP32 quotient), the closest point and its distance.
+__device__ __forceinline__ void ray_geom(const GeomDev &g, const ViewDev &V, int u, int v, RayF &r,
+                                         double &tc_out, double &dx, double &dy, double &dz) {
+    const double fu = (double)u, fv = (double)v;
+    dx = fma(fv, V.V[0], fma(fu, V.U[0], V.d0[0]));
+    dy = fma(fv, V.V[1], fma(fu, V.U[1], V.d0[1]));
+    dz = fma(fv, V.V[2], fma(fu, V.U[2], V.d0[2]));
+    const double A = fma(dx, dx, dy * dy);
+    const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
+    const float len = fsqrt(fma(fdx, fdx, fma(fdy, fdy, fdz * fdz)));
+    const float il = frcp(len);
+    r.ex = fdx * il;
+    r.ey = fdy * il;
+    r.ez = fdz * il;
+    r.flags = 0;
+    r.len = len;
+    r.dxd = dx;
+    r.dyd = dy;
+    double tc;
+    if (A > 0.0) {
+        const double B = fma(V.a[0], dx, V.a[1] * dy);
+        const float Af = (float)A;
+        const float rA = frcp(Af);
+        const float t0 = -(float)B * rA;
+        const double res = fma(-(double)t0, A, -B);  // -B - t0 A
+        tc = (double)t0 + (double)((float)res * rA);
+        r.inv_k = len * __builtin_amdgcn_rsqf(Af);
+    } else {
+        // parallel to the axis: put s = 0 at mid-height of the grid
+        r.flags |= RAY_AXIAL;
+        tc = (dz != 0.0) ? (0.5 * (g.h_min_d + g.h_max_d) - V.a[2]) / dz : 0.0;
+        tc = tc < 0.0 ? 0.0 : (tc > 1.0 ? 1.0 : tc);
+        r.inv_k = CYL_INF;
+    }
+    const double cxd = fma(tc, dx, V.a[0]);
+    const double cyd = fma(tc, dy, V.a[1]);
+    const double b2 = fma(cxd, cxd, cyd * cyd);
+    const float bf = fsqrt((float)b2);
+    r.b = bf;
+    r.blo = bf > 0.0f ? (float)fma(-(double)bf, (double)bf, b2) * (0.5f * frcp(bf)) : 0.0f;
+    r.cx = (float)cxd;
+    r.cy = (float)cyd;
+    const double zcd = fma(tc, dz, V.a[2]);
+    r.zc = (float)zcd;
+    r.zclo = (float)(zcd - (double)r.zc);
+    r.inv_ez = (fdz != 0.0f) ? len / fdz : CYL_INF;
+    tc_out = tc;
+    r.tcd = tc;
+    const float ftc = (float)tc;
+    float s0 = -ftc * len, s1 = (float)(1.0 - tc) * len;
+    // support interval with the same crossing formulas as the traversal
+    bool hit = true;
+    if (!(r.flags & RAY_AXIAL)) {
+        float w = shell_w(g.r_tab[g.n_r], r);
+        if (w < 0.0f) hit = false;
+        s0 = fmaxf(s0, -w);
+        s1 = fminf(s1, w);
+        if (bf == 0.0f && g.n_theta > 1) {
+            r.flags |= RAY_THRU;
+            r.it_in = sector_of(g, -r.ex, -r.ey);
+            r.it_out = sector_of(g, r.ex, r.ey);
+        }
+    } else {
+        float2 rt = g.r_tab[g.n_r];
+        if (!((rt.x - r.b) + (rt.y - r.blo) > 0.0f)) hit = false;
+    }
+    if (fdz != 0.0f) {
+        float t1 = plane_s(g.h_tab[0], r), t2 = plane_s(g.h_tab[g.n_h], r);
+        s0 = fmaxf(s0, fminf(t1, t2));
+        s1 = fminf(s1, fmaxf(t1, t2));
+    } else {
+        float2 lo = g.h_tab[0], hi = g.h_tab[g.n_h];
+        if (!(r.zc >= lo.x && r.zc < hi.x)) hit = false;
+    }
+    r.s_in = s0;
+    r.s_out = s1;
+    if (hit && s1 > s0) r.flags |= RAY_HIT;
+}
+
+// Closed-form row sum L_j in FP64: length inside the support minus the hole.
+__device__ __forceinline__ float row_sum_fp64(const GeomDev &g, const ViewDev &V, const RayF &r,
+                                              double tc, double dx, double dy, double dz) {
+    if (!(r.flags & RAY_HIT)) return 0.0f;
+    const double A = fma(dx, dx, dy * dy);
+    const double len = sqrt(A + dz * dz);
+    double lo = -tc * len, hi = (1.0 - tc) * len;
+    const double cxd = fma(tc, dx, V.a[0]), cyd = fma(tc, dy, V.a[1]);
+    const double b = sqrt(fma(cxd, cxd, cyd * cyd));
+    double ik = 0.0;
+    if (A > 0.0) {
+        ik = len / sqrt(A);
+        if (!(b < g.r_max_d)) return 0.0f;
+        double w = sqrt((g.r_max_d - b) * (g.r_max_d + b)) * ik;
+        lo = fmax(lo, -w);
+        hi = fmin(hi, w);
+    } else if (!(b < g.r_max_d)) {
+        return 0.0f;
+    }
+    if (dz != 0.0) {
+        const double zc = fma(tc, dz, V.a[2]);
+        double t1 = (g.h_min_d - zc) * len / dz, t2 = (g.h_max_d - zc) * len / dz;
+        lo = fmax(lo, fmin(t1, t2));
+        hi = fmin(hi, fmax(t1, t2));
+    }
+    if (!(hi > lo)) return 0.0f;
+    double L = hi - lo;
+    if (g.r_min_d > 0.0 && b < g.r_min_d) {
+        if (A > 0.0) {
+            double w = sqrt((g.r_min_d - b) * (g.r_min_d + b)) * ik;
+            L -= fmax(0.0, fmin(hi, w) - fmax(lo, -w));
+        } else {
+            L = 0.0;
+        }
+    }
+    return (float)fmax(L, 0.0);
+}
+
+// Cell at parameter s (indices clamped into the grid; ir = -1 inside the hole).
+__device__ __forceinline__ void cell_at(const GeomDev &g, const RayF &r, float s, int &ih, int &it,
+                                        int &ir) {
+    const float x = fmaf(s, r.ex, r.cx), y = fmaf(s, r.ey, r.cy), z = fmaf(s, r.ez, r.zc);
+    const float q = s / r.inv_k;
+    const float rr = fsqrt(fmaf(r.b, r.b, q * q));
+    int h = (int)floorf((z - g.h_min) / g.dh);
+    ih = h < 0 ? 0 : (h >= g.n_h ? g.n_h - 1 : h);
+    int ri = (int)floorf((rr - g.r_min) / g.dr);
+    ir = ri < -1 ? -1 : (ri >= g.n_r ? g.n_r - 1 : ri);
+    if (r.flags & RAY_THRU)
+        it = (s < 0.0f) ? r.it_in : r.it_out;
+    else
+        it = sector_of(g, x, y);
+}
+
+// ------------------------------------------------------------ traversal
+
+struct Walker {
+    int dir_h, dir_t;
+    bool r_in;
+    float s_z, s_r, s_t;
+
+    __device__ __forceinline__ float next_z(const GeomDev &g, const RayF &r, int ih, float s) const {
+        if (dir_h == 0) return CYL_INF;
+        return fmaxf(plane_s(g.h_tab[dir_h > 0 ? ih + 1 : ih], r), s);
+    }
+    __device__ __forceinline__ float next_r(const GeomDev &g, const RayF &r, int ir, float s) {
+        if (r.flags & RAY_AXIAL) return CYL_INF;
+        if (s < 0.0f && ir >= 0) {
+            float w = shell_w(g.r_tab[ir], r);
+            if (w >= 0.0f) {
+                r_in = true;
+                return fmaxf(-w, s);
+            }
+        }
+        r_in = false;
+        float w = shell_w(g.r_tab[ir + 1], r);
+        return w < 0.0f ? CYL_INF : fmaxf(w, s);
+    }
+    __device__ __forceinline__ float next_t(const GeomDev &g, const ViewDev &V, const RayF &r, int it,
+                                            float s) const {
+        if (r.flags & RAY_THRU) return s < 0.0f ? 0.0f : CYL_INF;
+        if (dir_t == 0) return CYL_INF;
+        // an edge-half-line meeting behind s means the start cell was one
+        // sector short (rounding at entry): cross it at once
+        const EdgeX x = edge_cross(g, V, r, dir_t > 0 ? it + 1 : it);
+        return x.on_edge ? fmaxf(x.s, s) : CYL_INF;
+    }
+};
+
+// Walk the ray from s to s_end starting in cell (ih, it, ir) and call
+// visit(ih, it, ir, length) for every piece with ir >= 0.
+template <class Visit>
+__device__ __forceinline__ void traverse(const GeomDev &g, const ViewDev &V, const RayF &r, float s,
+                                         const float s_end, int ih, int it, int ir, Visit &visit) {
+    Walker w;
+    w.dir_h = r.ez > 0.0f ? 1 : (r.ez < 0.0f ? -1 : 0);
+    const float cross = r.cx * r.ey - r.cy * r.ex;
+    w.dir_t = (g.n_theta == 1 || (r.flags & (RAY_AXIAL | RAY_THRU))) ? 0
+              : (cross > 0.0f ? 1 : (cross < 0.0f ? -1 : 0));
+    w.r_in = false;
+    w.s_z = w.next_z(g, r, ih, s);
+    w.s_r = w.next_r(g, r, ir, s);
+    w.s_t = (g.n_theta == 1) ? CYL_INF : w.next_t(g, V, r, it, s);
+    const int max_steps = 2 * g.n_r + g.n_theta + g.n_h + 8;
+    for (int n = 0; n < max_steps; ++n) {
+        const float sn = fminf(fminf(w.s_z, w.s_r), fminf(w.s_t, s_end));
+        if (ir >= 0) visit(ih, it, ir, sn - s);
+        s = sn;
+        if (!(sn < s_end)) break;
+        if (sn == w.s_z) {
+            ih += w.dir_h;
+            if ((unsigned)ih >= (unsigned)g.n_h) break;
+            w.s_z = w.next_z(g, r, ih, s);
+        } else if (sn == w.s_r) {
+            ir += w.r_in ? -1 : 1;
+            if (ir >= g.n_r) break;
+            w.s_r = w.next_r(g, r, ir, s);
+        } else {
+            if (r.flags & RAY_THRU) {
+                it = r.it_out;
+            } else {
+                it += w.dir_t;
+                it = it < 0 ? it + g.n_theta : (it >= g.n_theta ? it - g.n_theta : it);
+            }
+            w.s_t = w.next_t(g, V, r, it, s);
+        }
+    }
+}
+
+// ------------------------------------------------------------ forward projection
+
+// 8 x 8 pixel tile per wave; blockIdx.y = view offset.
+template <int VT, int PT, bool SART>
+__global__ __launch_bounds__(64) void fp_kernel(GeomDev g, const void *__restrict__ vol,
+                                                void *__restrict__ proj, int view_begin,
+                                                const void *__restrict__ pw, int pwt,
+                                                float *__restrict__ rho) {
+    const int k = view_begin + blockIdx.y;
+    const int tiles_u = (g.cols + 7) >> 3;
+    const int u = (blockIdx.x % tiles_u) * 8 + (threadIdx.x & 7);
+    const int v = (blockIdx.x / tiles_u) * 8 + (threadIdx.x >> 3);
+    if (u >= g.cols || v >= g.rows) return;
+    const ViewDev &V = g.views[k];
+    RayF r;
+    double tc, dx, dy, dz;
+    ray_geom(g, V, u, v, r, tc, dx, dy, dz);
+    float acc = 0.0f;
+    if (r.flags & RAY_HIT) {
+        int ih, it, ir;
+        cell_at(g, r, r.s_in, ih, it, ir);
+        const int nt = g.n_theta, nr = g.n_r;
+        auto visit = [&](int h, int t, int q, float len) {
+            acc = fmaf(len, Store<VT>::ld(vol, (size_t)((h * nt + t) * nr + q)), acc);
+        };
+        traverse(g, V, r, r.s_in, r.s_out, ih, it, ir, visit);
+    }
+    const size_t j = ((size_t)k * g.rows + v) * g.cols + u;
+    if (!SART) {
+        Store<PT>::st(proj, j, acc);
+    } else {
+        const float L = row_sum_fp64(g, V, r, tc, dx, dy, dz);
+        const float p = Store<PT>::ld(proj, j);
+        const float w = pw ? ld_any(pw, pwt, j) : 1.0f;
+        rho[(size_t)v * g.cols + u] = (L > 0.0f) ? w * (p - acc) / L : 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(64) void rowsum_kernel(GeomDev g, float *__restrict__ out, int view_begin) {
+    const int k = view_begin + blockIdx.y;
+    const int tiles_u = (g.cols + 7) >> 3;
+    const int u = (blockIdx.x % tiles_u) * 8 + (threadIdx.x & 7);
+    const int v = (blockIdx.x / tiles_u) * 8 + (threadIdx.x >> 3);
+    if (u >= g.cols || v >= g.rows) return;
+    const ViewDev &V = g.views[k];
+    RayF r;
+    double tc, dx, dy, dz;
+    ray_geom(g, V, u, v, r, tc, dx, dy, dz);
+    out[((size_t)k * g.rows + v) * g.cols + u] = row_sum_fp64(g, V, r, tc, dx, dy, dz);
+}
+
+// ------------------------------------------------------------ back-projection
+
+struct Block {
+    int hA, hB, tA, tB, rA, rB;
+};
+
+__device__ __forceinline__ Block block_of(const GeomDev &g, int b) {
+    Block B;
+    const int ir = b % g.nbr;
+    const int rest = b / g.nbr;
+    const int itb = rest % g.nbt;
+    const int ihb = rest / g.nbt;
+    B.hA = ihb * g.bh;
+    B.hB = min(B.hA + g.bh, g.n_h);
+    B.tA = itb * g.bt;
+    B.tB = min(B.tA + g.bt, g.n_theta);
+    B.rA = ir * g.br;
+    B.rB = min(B.rA + g.br, g.n_r);
+    return B;
+}
+
+__device__ __forceinline__ float wave_min(float x) {
+    for (int o = 32; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o));
+    return x;
+}
+__device__ __forceinline__ float wave_max(float x) {
+    for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o));
+    return x;
+}
+
+// Projection of one bounding point of the block's convex hull
+// slab x wedge x disc(r_B) in view V, for point index `pt` (two z levels per
+// polygon corner; the polygon circumscribes the outer arc).  Points with
+// pt >= count leave the box untouched.  Sets `behind` if the point is not in
+// front of the source.
+__device__ __forceinline__ void footprint_point(const GeomDev &g, const ViewDev &V, const Block &B, int pt,
+                                                float &umin, float &umax, float &vmin, float &vmax,
+                                                float &behind) {
+    const float rO = g.r_tab[B.rB].x * (1.0f + 1e-6f) + 1e-6f;
+    const float rI = g.r_tab[B.rA].x;
+    const bool full = (B.tB - B.tA) >= g.n_theta;
+    const int pi = pt >> 1;
+    int npoly;
+    float px = 0.0f, py = 0.0f;
+    if (full) {
+        npoly = 4;
+        const float c = rO * 1.41421356f * (1.0f + 1e-6f);
+        px = (pi == 0 || pi == 3) ? c : -c;
+        py = (pi < 2) ? c : -c;
+    } else {
+        const float thA = g.theta0 + B.tA * g.dtheta;
+        const float om = (B.tB - B.tA) * g.dtheta;
+        const int nseg = max(1, (int)ceilf(om * (4.0f / 3.14159265f) - 1e-4f));
+        const float del = om / nseg;
+        const float rc = rO / cosf(0.5f * del) * (1.0f + 1e-6f);
+        npoly = nseg + 3;
+        if (pi <= nseg) {
+            const float ang = thA + pi * del;
+            px = rc * cosf(ang);
+            py = rc * sinf(ang);
+        } else {
+            const float ang = (pi == nseg + 1) ? thA : thA + om;
+            px = rI * cosf(ang);
+            py = rI * sinf(ang);
+        }
+    }
+    if (pi >= npoly) return;
+    const float pz = (pt & 1) ? g.h_tab[B.hB].x + 1e-5f : g.h_tab[B.hA].x - 1e-5f;
+    const float X = px - V.af[0], Y = py - V.af[1], Z = pz - V.af[2];
+    const float lam = V.Qi[0] * X + V.Qi[1] * Y + V.Qi[2] * Z;
+    const float uu = V.Qi[3] * X + V.Qi[4] * Y + V.Qi[5] * Z;
+    const float vv = V.Qi[6] * X + V.Qi[7] * Y + V.Qi[8] * Z;
+    if (lam > 1e-6f) {
+        const float il = 1.0f / lam;
+        umin = fminf(umin, uu * il);
+        umax = fmaxf(umax, uu * il);
+        vmin = fminf(vmin, vv * il);
+        vmax = fmaxf(vmax, vv * il);
+    } else {
+        behind = 1.0f;
+    }
+}
+
+// Pixel index box from the projected extent (with a small margin, clipped to
+// the detector).  Returns false if empty.
+__device__ __forceinline__ bool footprint_box(const GeomDev &g, float umin, float umax, float vmin, float vmax,
+                                              float behind, int &u0, int &u1, int &v0, int &v1) {
+    if (behind > 0.0f) {
+        u0 = 0;
+        u1 = g.cols - 1;
+        v0 = 0;
+        v1 = g.rows - 1;
+        return true;
+    }
+    const float m = 0.05f;
+    float fu0 = fmaxf(ceilf(umin - m), 0.0f), fu1 = fminf(floorf(umax + m), (float)(g.cols - 1));
+    float fv0 = fmaxf(ceilf(vmin - m), 0.0f), fv1 = fminf(floorf(vmax + m), (float)(g.rows - 1));
+    if (!(fu1 >= fu0 && fv1 >= fv0)) return false;
+    u0 = (int)fu0;
+    u1 = (int)fu1;
+    v0 = (int)fv0;
+    v1 = (int)fv1;
+    return true;
+}
+
+// Detector box of the block in view V; the whole wave participates (each lane
+// projects one hull point, then min/max across the wave).
+__device__ bool footprint(const GeomDev &g, const ViewDev &V, const Block &B, int &u0, int &u1, int &v0,
+                          int &v1) {
+    float umin = CYL_INF, umax = -CYL_INF, vmin = CYL_INF, vmax = -CYL_INF, behind = 0.0f;
+    footprint_point(g, V, B, threadIdx.x & 63, umin, umax, vmin, vmax, behind);
+    umin = wave_min(umin);
+    umax = wave_max(umax);
+    vmin = wave_min(vmin);
+    vmax = wave_max(vmax);
+    behind = wave_max(behind);
+    return footprint_box(g, umin, umax, vmin, vmax, behind, u0, u1, v0, v1);
+}
+
+// Parameter interval of the ray inside the block hull (slab x wedge x disc),
+// from the same crossing formulas as the traversal.
+__device__ __forceinline__ bool clip_block(const GeomDev &g, const ViewDev &V, const RayF &r, const Block &B,
+                                           float &s0, float &s1) {
+    s0 = r.s_in;
+    s1 = r.s_out;
+    if (r.ez != 0.0f) {
+        float t1 = plane_s(g.h_tab[B.hA], r), t2 = plane_s(g.h_tab[B.hB], r);
+        s0 = fmaxf(s0, fminf(t1, t2));
+        s1 = fminf(s1, fmaxf(t1, t2));
+    } else if (!(r.zc >= g.h_tab[B.hA].x && r.zc < g.h_tab[B.hB].x)) {
+        return false;
+    }
+    if (!(r.flags & RAY_AXIAL)) {
+        float w = shell_w(g.r_tab[B.rB], r);
+        if (w < 0.0f) return false;
+        s0 = fmaxf(s0, -w);
+        s1 = fminf(s1, w);
+    } else {
+        float2 rt = g.r_tab[B.rB];
+        if (!((rt.x - r.b) + (rt.y - r.blo) > 0.0f)) return false;
+    }
+    if (B.tB - B.tA < g.n_theta) {
+        // lower edge: n_A . p >= 0 ; upper edge: n_B . p <= 0
+        for (int e = 0; e < 2; ++e) {
+            const EdgeX x = edge_cross(g, V, r, e == 0 ? B.tA : B.tB);
+            const float sg = e == 0 ? 1.0f : -1.0f;
+            if (x.ne == 0.0f) {
+                if (sg * x.nc < 0.0f) return false;
+                continue;
+            }
+            if (sg * x.ne > 0.0f)
+                s0 = fmaxf(s0, x.s);
+            else
+                s1 = fminf(s1, x.s);
+        }
+    }
+    return s1 > s0;
+}
+
+// Trace ray (u, v) of view V through block B and add t_jm * yj (and t_jm if
+// COLSUM) into the block accumulators.
+template <bool COLSUM>
+__device__ __forceinline__ void bp_ray(const GeomDev &g, const ViewDev &V, const Block &B, int u, int v,
+                                       float yj, float *acc_c, float *acc_n) {
+    const int wt = B.tB - B.tA, wr = B.rB - B.rA;
+    RayF r;
+    double tc, dx, dy, dz;
+    ray_geom(g, V, u, v, r, tc, dx, dy, dz);
+    if (!(r.flags & RAY_HIT)) return;
+    float s0, s1;
+    if (!clip_block(g, V, r, B, s0, s1)) return;
+    // the hull includes the block's inner hole r < r_A: split the
+    // interval there so the walk covers the block cells only
+    float pa0 = s0, pa1 = s1, pb0 = 1.0f, pb1 = 0.0f;
+    if (g.r_tab[B.rA].x > 0.0f) {
+        if (r.flags & RAY_AXIAL) {
+            float2 rt = g.r_tab[B.rA];
+            if ((rt.x - r.b) + (rt.y - r.blo) > 0.0f) return;
+        } else {
+            const float wA = shell_w(g.r_tab[B.rA], r);
+            if (wA >= 0.0f) {
+                pa1 = fminf(s1, -wA);
+                pb0 = fmaxf(s0, wA);
+                pb1 = s1;
+            }
+        }
+    }
+    auto visit = [&](int h, int t, int q, float len) {
+        if (q >= B.rA && q < B.rB && h >= B.hA && h < B.hB && t >= B.tA && t < B.tB) {
+            const int loc = ((h - B.hA) * wt + (t - B.tA)) * wr + (q - B.rA);
+            atomicAdd(&acc_c[loc], len * yj);
+            if (COLSUM) atomicAdd(&acc_n[loc], len);
+        }
+    };
+    for (int piece = 0; piece < 2; ++piece) {
+        const float a0 = piece ? pb0 : pa0, a1 = piece ? pb1 : pa1;
+        if (!(a1 > a0)) continue;
+        int ih, it, ir;
+        cell_at(g, r, a0, ih, it, ir);
+        ih = ih < B.hA ? B.hA : (ih >= B.hB ? B.hB - 1 : ih);
+        ir = ir < B.rA ? B.rA : (ir >= B.rB ? B.rB - 1 : ir);
+        if (it < B.tA || it >= B.tB) {
+            // nearest block edge on the circle
+            int dlo = B.tA - it;
+            if (dlo < 0) dlo += g.n_theta;
+            int dhi = it - (B.tB - 1);
+            if (dhi < 0) dhi += g.n_theta;
+            it = dlo <= dhi ? B.tA : B.tB - 1;
+        }
+        traverse(g, V, r, a0, a1, ih, it, ir, visit);
+    }
+}
+
+// One wave owns one block of cells; it loops over the views, over the
+// detector pixels of the block footprint, traces each ray through the block
+// hull and accumulates c_m = sum t_jm y_j and n_m = sum t_jm in wave-private
+// LDS.  MODE 0: vol = (accumulate ? vol : 0) + c.  MODE 1 (SART, one view):
+// vol += lam * wv * c / n where n > 0.
+template <int VT, int PT, int MODE>
+__global__ __launch_bounds__(64) void bp_kernel(GeomDev g, const void *__restrict__ y, int view_begin,
+                                                int view_end, void *__restrict__ vol, int accumulate,
+                                                const float *__restrict__ rho,
+                                                const void *__restrict__ vw, int vwt, float lam,
+                                                int nonneg) {
+    __shared__ float acc_c[kBlockCells];
+    __shared__ float acc_n[kBlockCells];
+    const int lane = threadIdx.x;
+    const Block B = block_of(g, blockIdx.x);
+    const int wt = B.tB - B.tA, wr = B.rB - B.rA;
+    const int ncell = (B.hB - B.hA) * wt * wr;
+    for (int i = lane; i < ncell; i += 64) {
+        acc_c[i] = 0.0f;
+        acc_n[i] = 0.0f;
+    }
+    __syncthreads();
+    for (int k = view_begin; k < view_end; ++k) {
+        const ViewDev &V = g.views[k];
+        int u0, u1, v0, v1;
+        if (!footprint(g, V, B, u0, u1, v0, v1)) continue;
+        const int nu = u1 - u0 + 1;
+        const int npix = nu * (v1 - v0 + 1);
+        for (int base = 0; base < npix; base += 64) {
+            const int p = base + lane;
+            if (p >= npix) continue;
+            const int v = v0 + p / nu;
+            const int u = u0 + p % nu;
+            float yj;
+            if (MODE == 1)
+                yj = rho[(size_t)v * g.cols + u];
+            else
+                yj = Store<PT>::ld(y, ((size_t)k * g.rows + v) * g.cols + u);
+            if (MODE == 0 && yj == 0.0f) continue;
+            bp_ray<(MODE == 1)>(g, V, B, u, v, yj, acc_c, acc_n);
+        }
+    }
+    __syncthreads();
+    for (int i = lane; i < ncell; i += 64) {
+        const int q = i % wr;
+        const int t = (i / wr) % wt;
+        const int h = i / (wr * wt);
+        const size_t gi = ((size_t)(B.hA + h) * g.n_theta + (B.tA + t)) * g.n_r + (B.rA + q);
+        if (MODE == 0) {
+            const float base = accumulate ? Store<VT>::ld(vol, gi) : 0.0f;
+            Store<VT>::st(vol, gi, base + acc_c[i]);
+        } else {
+            const float n = acc_n[i];
+            if (n > 0.0f) {
+                const float w = vw ? ld_any(vw, vwt, gi) : 1.0f;
+                float m = Store<VT>::ld(vol, gi) + lam * w * acc_c[i] / n;
+                if (nonneg && m < 0.0f) m = 0.0f;
+                Store<VT>::st(vol, gi, m);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ launchers
+
+static int launch_check(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("%s: launch failed: %s", what, hipGetErrorString(e));
+        return CYL_EDEVICE;
+    }
+    return CYL_OK;
+}
+
+template <int VT, int PT>
+static void launch_fp_t(const cyl_geom *G, const void *vol, void *proj, int vb, int nv, bool sart,
+                        const void *pw, int pwt, float *rho, hipStream_t st) {
+    const GeomDev &g = G->dev;
+    dim3 grid(((g.cols + 7) / 8) * ((g.rows + 7) / 8), nv);
+    if (sart)
+        hipLaunchKernelGGL((fp_kernel<VT, PT, true>), grid, dim3(64), 0, st, g, vol, proj, vb, pw, pwt, rho);
+    else
+        hipLaunchKernelGGL((fp_kernel<VT, PT, false>), grid, dim3(64), 0, st, g, vol, proj, vb, pw, pwt, rho);
+}
+
+template <int VT>
+static void launch_fp_v(const cyl_geom *G, const void *vol, void *proj, int pt, int vb, int nv, bool sart,
+                        const void *pw, int pwt, float *rho, hipStream_t st) {
+    switch (pt) {
+        case CYL_F32: launch_fp_t<VT, CYL_F32>(G, vol, proj, vb, nv, sart, pw, pwt, rho, st); break;
+        case CYL_F16: launch_fp_t<VT, CYL_F16>(G, vol, proj, vb, nv, sart, pw, pwt, rho, st); break;
+        default: launch_fp_t<VT, CYL_BF16>(G, vol, proj, vb, nv, sart, pw, pwt, rho, st); break;
+    }
+}
+
+static void launch_fp(const cyl_geom *G, const void *vol, int vt, void *proj, int pt, int vb, int nv, bool sart,
+                      const void *pw, int pwt, float *rho, hipStream_t st) {
+    switch (vt) {
+        case CYL_F32: launch_fp_v<CYL_F32>(G, vol, proj, pt, vb, nv, sart, pw, pwt, rho, st); break;
+        case CYL_F16: launch_fp_v<CYL_F16>(G, vol, proj, pt, vb, nv, sart, pw, pwt, rho, st); break;
+        default: launch_fp_v<CYL_BF16>(G, vol, proj, pt, vb, nv, sart, pw, pwt, rho, st); break;
+    }
+}
+
+template <int VT, int PT>
+static void launch_bp_t(const cyl_geom *G, const void *y, int vb, int ve, void *vol, int accumulate, bool sart,
+                        const float *rho, const void *vw, int vwt, float lam, int nonneg, hipStream_t st) {
+    const GeomDev &g = G->dev;
+    dim3 grid(g.nbh * g.nbt * g.nbr);
+    if (sart)
+        hipLaunchKernelGGL((bp_kernel<VT, PT, 1>), grid, dim3(64), 0, st, g, y, vb, ve, vol, accumulate, rho, vw,
+                           vwt, lam, nonneg);
+    else
+        hipLaunchKernelGGL((bp_kernel<VT, PT, 0>), grid, dim3(64), 0, st, g, y, vb, ve, vol, accumulate, rho, vw,
+                           vwt, lam, nonneg);
+}
+
+template <int VT>
+static void launch_bp_v(const cyl_geom *G, const void *y, int pt, int vb, int ve, void *vol, int accumulate,
+                        bool sart, const float *rho, const void *vw, int vwt, float lam, int nonneg,
+                        hipStream_t st) {
+    if (sart) {  // the SART update reads FP32 residuals, not the projections
+        launch_bp_t<VT, CYL_F32>(G, y, vb, ve, vol, accumulate, sart, rho, vw, vwt, lam, nonneg, st);
+        return;
+    }
+    switch (pt) {
+        case CYL_F32: launch_bp_t<VT, CYL_F32>(G, y, vb, ve, vol, accumulate, sart, rho, vw, vwt, lam, nonneg, st); break;
+        case CYL_F16: launch_bp_t<VT, CYL_F16>(G, y, vb, ve, vol, accumulate, sart, rho, vw, vwt, lam, nonneg, st); break;
+        default: launch_bp_t<VT, CYL_BF16>(G, y, vb, ve, vol, accumulate, sart, rho, vw, vwt, lam, nonneg, st); break;
+    }
+}
+
+static void launch_bp(const cyl_geom *G, const void *y, int pt, int vb, int ve, void *vol, int vt, int accumulate,
+                      bool sart, const float *rho, const void *vw, int vwt, float lam, int nonneg, hipStream_t st) {
+    switch (vt) {
+        case CYL_F32: launch_bp_v<CYL_F32>(G, y, pt, vb, ve, vol, accumulate, sart, rho, vw, vwt, lam, nonneg, st); break;
+        case CYL_F16: launch_bp_v<CYL_F16>(G, y, pt, vb, ve, vol, accumulate, sart, rho, vw, vwt, lam, nonneg, st); break;
+        default: launch_bp_v<CYL_BF16>(G, y, pt, vb, ve, vol, accumulate, sart, rho, vw, vwt, lam, nonneg, st); break;
+    }
+}
+
+// Makes the geometry's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        hipGetDevice(&prev);
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        hipGetDevice(&cur);
+        if (prev >= 0 && cur != prev) hipSetDevice(prev);
+    }
+};
+
+static int check_range(const cyl_geom *G, int32_t vb, int32_t ve, const char *what) {
+    if (vb < 0 || ve < vb || ve > G->n_views) {
+        set_error("%s: view range [%d, %d) outside [0, %d)", what, vb, ve, G->n_views);
+        return CYL_EINVAL;
+    }
+    return CYL_OK;
+}
+
+}  // namespace cyl
+
+using namespace cyl;
+
+extern "C" int cyl_fp(const cyl_geom *G, const void *vol, cyl_dtype vt, void *proj, cyl_dtype pt,
+                      int32_t view_begin, int32_t view_end, void *hip_stream) {
+    if (!G || !vol || !proj) {
+        set_error("cyl_fp: NULL argument");
+        return CYL_EINVAL;
+    }
+    int rc;
+    if ((rc = check_dtype(vt, "cyl_fp volume")) || (rc = check_dtype(pt, "cyl_fp projections")) ||
+        (rc = check_range(G, view_begin, view_end, "cyl_fp")))
+        return rc;
+    if (view_end == view_begin) return CYL_OK;
+    DeviceGuard dg(G->device);
+    if (!dg.ok) {
+        set_error("cyl_fp: cannot select device %d", G->device);
+        return CYL_EDEVICE;
+    }
+    launch_fp(G, vol, vt, proj, pt, view_begin, view_end - view_begin, false, nullptr, 0, nullptr,
+              (hipStream_t)hip_stream);
+    return launch_check("cyl_fp");
+}
+
+extern "C" int cyl_bp(const cyl_geom *G, const void *proj, cyl_dtype pt, void *vol, cyl_dtype vt,
+                      int32_t view_begin, int32_t view_end, int32_t accumulate, void *hip_stream) {
+    if (!G || !vol || !proj) {
+        set_error("cyl_bp: NULL argument");
+        return CYL_EINVAL;
+    }
+    int rc;
+    if ((rc = check_dtype(vt, "cyl_bp volume")) || (rc = check_dtype(pt, "cyl_bp projections")) ||
+        (rc = check_range(G, view_begin, view_end, "cyl_bp")))
+        return rc;
+    if (view_end == view_begin && accumulate) return CYL_OK;
+    DeviceGuard dg(G->device);
+    if (!dg.ok) {
+        set_error("cyl_bp: cannot select device %d", G->device);
+        return CYL_EDEVICE;
+    }
+    launch_bp(G, proj, pt, view_begin, view_end, vol, vt, accumulate ? 1 : 0, false, nullptr, nullptr, 0, 0.0f, 0,
+              (hipStream_t)hip_stream);
+    return launch_check("cyl_bp");
+}
+
+extern "C" int cyl_row_sums(const cyl_geom *G, float *out, int32_t view_begin, int32_t view_end,
+                            void *hip_stream) {
+    if (!G || !out) {
+        set_error("cyl_row_sums: NULL argument");
+        return CYL_EINVAL;
+    }
+    int rc;
+    if ((rc = check_range(G, view_begin, view_end, "cyl_row_sums"))) return rc;
+    if (view_end == view_begin) return CYL_OK;
+    DeviceGuard dg(G->device);
+    if (!dg.ok) {
+        set_error("cyl_row_sums: cannot select device %d", G->device);
+        return CYL_EDEVICE;
+    }
+    const GeomDev &g = G->dev;
+    dim3 grid(((g.cols + 7) / 8) * ((g.rows + 7) / 8), view_end - view_begin);
+    hipLaunchKernelGGL(rowsum_kernel, grid, dim3(64), 0, (hipStream_t)hip_stream, g, out, view_begin);
+    return launch_check("cyl_row_sums");
+}
+
+extern "C" size_t cyl_sart_workspace_bytes(const cyl_geom *G, const cyl_sart_params *) {
+    if (!G) return 0;
+    size_t n = (size_t)G->rows * G->cols * sizeof(float);
+    return (n + 255) & ~(size_t)255;
+}
+
+extern "C" int cyl_sart_run(const cyl_geom *G, const cyl_sart_params *P, const void *proj, cyl_dtype pt,
+                            const void *pw, cyl_dtype pwt, const void *vw, cyl_dtype vwt, void *vol,
+                            cyl_dtype vt, void *workspace, size_t ws_bytes, void *hip_stream) {
+    if (!G || !P || !proj || !vol) {
+        set_error("cyl_sart_run: NULL argument");
+        return CYL_EINVAL;
+    }
+    int rc;
+    if ((rc = check_dtype(vt, "cyl_sart_run volume")) || (rc = check_dtype(pt, "cyl_sart_run projections")))
+        return rc;
+    if (pw && (rc = check_dtype(pwt, "cyl_sart_run projection weights"))) return rc;
+    if (vw && (rc = check_dtype(vwt, "cyl_sart_run voxel weights"))) return rc;
+    if (P->n_iter < 0 || P->start_iter < 0 || P->start_view < 0 || P->start_view > G->n_views) {
+        set_error("cyl_sart_run: invalid iteration counts (n_iter %d, start %d/%d)", P->n_iter, P->start_iter,
+                  P->start_view);
+        return CYL_EINVAL;
+    }
+    if (!std::isfinite(P->lambda)) {
+        set_error("cyl_sart_run: lambda must be finite");
+        return CYL_EINVAL;
+    }
+    if (P->view_order)
+        for (int i = 0; i < G->n_views; ++i)
+            if (P->view_order[i] < 0 || P->view_order[i] >= G->n_views) {
+                set_error("cyl_sart_run: view_order[%d] = %d out of range", i, P->view_order[i]);
+                return CYL_EINVAL;
+            }
+    const size_t need = cyl_sart_workspace_bytes(G, P);
+    if (!workspace || ws_bytes < need) {
+        set_error("cyl_sart_run: workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+        return CYL_EINVAL;
+    }
+    if (P->start_iter >= P->n_iter) return CYL_OK;
+    DeviceGuard dg(G->device);
+    if (!dg.ok) {
+        set_error("cyl_sart_run: cannot select device %d", G->device);
+        return CYL_EDEVICE;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    float *rho = (float *)workspace;
+    const float lam = (float)P->lambda;
+    for (int it = P->start_iter; it < P->n_iter; ++it) {
+        const int kv0 = (it == P->start_iter) ? P->start_view : 0;
+        for (int kk = kv0; kk < G->n_views; ++kk) {
+            const int k = P->view_order ? P->view_order[kk] : kk;
+            launch_fp(G, vol, vt, const_cast<void *>(proj), pt, k, 1, true, pw, pwt, rho, st);
+            launch_bp(G, nullptr, CYL_F32, k, k + 1, vol, vt, 0, true, rho, vw, vwt, lam, P->nonneg, st);
+        }
+        if ((rc = launch_check("cyl_sart_run"))) return rc;
+    }
+    return CYL_OK;
+}
+
+extern "C" int cyl_sart_residual(const cyl_geom *G, int32_t view, const void *proj, cyl_dtype pt, const void *pw,
+                                 cyl_dtype pwt, const void *vol, cyl_dtype vt, void *workspace, size_t ws_bytes,
+                                 void *hip_stream) {
+    if (!G || !proj || !vol) {
+        set_error("cyl_sart_residual: NULL argument");
+        return CYL_EINVAL;
+    }
+    int rc;
+    if ((rc = check_dtype(vt, "cyl_sart_residual volume")) ||
+        (rc = check_dtype(pt, "cyl_sart_residual projections")))
+        return rc;
+    if (pw && (rc = check_dtype(pwt, "cyl_sart_residual projection weights"))) return rc;
+    if (view < 0 || view >= G->n_views) {
+        set_error("cyl_sart_residual: view %d outside [0, %d)", view, G->n_views);
+        return CYL_EINVAL;
+    }
+    const size_t need = cyl_sart_workspace_bytes(G, nullptr);
+    if (!workspace || ws_bytes < need) {
+        set_error("cyl_sart_residual: workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+        return CYL_EINVAL;
+    }
+    DeviceGuard dg(G->device);
+    if (!dg.ok) {
+        set_error("cyl_sart_residual: cannot select device %d", G->device);
+        return CYL_EDEVICE;
+    }
+    launch_fp(G, vol, vt, const_cast<void *>(proj), pt, view, 1, true, pw, pwt, (float *)workspace,
+              (hipStream_t)hip_stream);
+    return launch_check("cyl_sart_residual");
+}
+
+extern "C" int cyl_sart_update(const cyl_geom *G, int32_t view, double lambda, int32_t nonneg, const void *vw,
+                               cyl_dtype vwt, void *vol, cyl_dtype vt, const void *workspace, size_t ws_bytes,
+                               void *hip_stream) {
+    if (!G || !vol) {
+        set_error("cyl_sart_update: NULL argument");
+        return CYL_EINVAL;
+    }
+    int rc;
+    if ((rc = check_dtype(vt, "cyl_sart_update volume"))) return rc;
+    if (vw && (rc = check_dtype(vwt, "cyl_sart_update voxel weights"))) return rc;
+    if (view < 0 || view >= G->n_views) {
+        set_error("cyl_sart_update: view %d outside [0, %d)", view, G->n_views);
+        return CYL_EINVAL;
+    }
+    if (!std::isfinite(lambda)) {
+        set_error("cyl_sart_update: lambda must be finite");
+        return CYL_EINVAL;
+    }
+    const size_t need = cyl_sart_workspace_bytes(G, nullptr);
+    if (!workspace || ws_bytes < need) {
+        set_error("cyl_sart_update: workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+        return CYL_EINVAL;
+    }
+    DeviceGuard dg(G->device);
+    if (!dg.ok) {
+        set_error("cyl_sart_update: cannot select device %d", G->device);
+        return CYL_EDEVICE;
+    }
+    launch_bp(G, nullptr, CYL_F32, view, view + 1, vol, vt, 0, true, (const float *)workspace, vw, vwt,
+              (float)lambda, nonneg, (hipStream_t)hip_stream);
+    return launch_check("cyl_sart_update");
+}

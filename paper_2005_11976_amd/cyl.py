@@ -1,0 +1,271 @@
+"""Thin Python binding of libcyl (argument marshalling only).
+
+Every step of the path runs in the HIP kernels of libcyl.so; this module only
+turns torch tensors and scan descriptions into the C-ABI calls declared in
+include/cyl.h.  It raises if the library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcyl.so")
+
+CYL_F32, CYL_F16, CYL_BF16 = 0, 1, 2
+CYL_OK, CYL_EINVAL, CYL_ENOMEM, CYL_EDEVICE, CYL_EUNSUPPORTED = 0, -1, -2, -3, -4
+
+EXPORTS = ["cyl_geom_create", "cyl_geom_destroy", "cyl_fp", "cyl_bp", "cyl_row_sums",
+           "cyl_sart_workspace_bytes", "cyl_sart_run", "cyl_sart_residual", "cyl_sart_update",
+           "cyl_last_error", "cyl_version"]
+
+
+class CylError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libcyl error %d: %s" % (code, msg))
+        self.code = code
+
+
+class cyl_grid(C.Structure):
+    _fields_ = [("n_h", C.c_int32), ("n_theta", C.c_int32), ("n_r", C.c_int32),
+                ("r_min", C.c_double), ("r_max", C.c_double), ("h_min", C.c_double),
+                ("h_max", C.c_double), ("theta0", C.c_double)]
+
+
+class cyl_traj(C.Structure):
+    _fields_ = [("n_views", C.c_int32), ("det_rows", C.c_int32), ("det_cols", C.c_int32),
+                ("views", C.POINTER(C.c_double))]
+
+
+class cyl_pose(C.Structure):
+    _fields_ = [("R", C.c_double * 9), ("T", C.c_double * 3)]
+
+
+class cyl_sart_params(C.Structure):
+    _fields_ = [("n_iter", C.c_int32), ("lam", C.c_double), ("nonneg", C.c_int32),
+                ("view_order", C.POINTER(C.c_int32)), ("start_iter", C.c_int32),
+                ("start_view", C.c_int32)]
+
+
+_lib = None
+
+
+def declare(lib):
+    """Attach argument/return types of the C ABI to a loaded library."""
+    vp, i32, P = C.c_void_p, C.c_int32, C.POINTER
+    lib.cyl_geom_create.argtypes = [P(cyl_grid), P(cyl_traj), P(cyl_pose), C.c_int, P(vp)]
+    lib.cyl_geom_create.restype = C.c_int
+    lib.cyl_geom_destroy.argtypes = [vp]
+    lib.cyl_geom_destroy.restype = None
+    lib.cyl_fp.argtypes = [vp, vp, C.c_int, vp, C.c_int, i32, i32, vp]
+    lib.cyl_fp.restype = C.c_int
+    lib.cyl_bp.argtypes = [vp, vp, C.c_int, vp, C.c_int, i32, i32, i32, vp]
+    lib.cyl_bp.restype = C.c_int
+    lib.cyl_row_sums.argtypes = [vp, vp, i32, i32, vp]
+    lib.cyl_row_sums.restype = C.c_int
+    lib.cyl_sart_workspace_bytes.argtypes = [vp, P(cyl_sart_params)]
+    lib.cyl_sart_workspace_bytes.restype = C.c_size_t
+    lib.cyl_sart_run.argtypes = [vp, P(cyl_sart_params), vp, C.c_int, vp, C.c_int, vp, C.c_int,
+                                 vp, C.c_int, vp, C.c_size_t, vp]
+    lib.cyl_sart_run.restype = C.c_int
+    lib.cyl_sart_residual.argtypes = [vp, i32, vp, C.c_int, vp, C.c_int, vp, C.c_int, vp,
+                                      C.c_size_t, vp]
+    lib.cyl_sart_residual.restype = C.c_int
+    lib.cyl_sart_update.argtypes = [vp, i32, C.c_double, i32, vp, C.c_int, vp, C.c_int, vp,
+                                    C.c_size_t, vp]
+    lib.cyl_sart_update.restype = C.c_int
+    lib.cyl_last_error.argtypes = []
+    lib.cyl_last_error.restype = C.c_char_p
+    lib.cyl_version.argtypes = []
+    lib.cyl_version.restype = C.c_char_p
+    return lib
+
+
+def lib():
+    """The loaded libcyl.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libcyl.so not found at %s: build it with "
+                               "`python -m paper_2005_11976_amd.build`" % LIB_PATH)
+        _lib = declare(C.CDLL(LIB_PATH))
+    return _lib
+
+
+def _check(rc, L=None):
+    if rc != CYL_OK:
+        L = L or lib()
+        raise CylError(rc, L.cyl_last_error().decode())
+
+
+def grid_struct(g):
+    return cyl_grid(g.n_h, g.n_theta, g.n_r, g.r_min, g.r_max, g.h_min, g.h_max, g.theta0)
+
+
+def pose_struct(R, T):
+    p = cyl_pose()
+    p.R[:] = [float(x) for x in np.asarray(R, dtype=np.float64).ravel()]
+    p.T[:] = [float(x) for x in np.asarray(T, dtype=np.float64).ravel()]
+    return p
+
+
+def _dtype_code(t):
+    import torch
+    codes = {torch.float32: CYL_F32, torch.float16: CYL_F16, torch.bfloat16: CYL_BF16}
+    if t.dtype not in codes:
+        raise TypeError("unsupported dtype %s (float32, float16, bfloat16)" % t.dtype)
+    return codes[t.dtype]
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class Geometry:
+    """A libcyl geometry (grid, trajectory, pose) resident on one GPU."""
+
+    def __init__(self, scan, device=0, _lib=None):
+        self._L = _lib or lib()
+        self.scan = scan
+        self.device = device
+        views = np.ascontiguousarray(scan.views, dtype=np.float64)
+        self._views = views
+        traj = cyl_traj(scan.n_views, scan.det_rows, scan.det_cols,
+                        views.ctypes.data_as(C.POINTER(C.c_double)))
+        g = grid_struct(scan.grid)
+        pose = pose_struct(scan.R, scan.T)
+        h = C.c_void_p()
+        _check(self._L.cyl_geom_create(C.byref(g), C.byref(traj), C.byref(pose), device,
+                                       C.byref(h)), self._L)
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self._L.cyl_geom_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- checks ---------------------------------------------------------------
+    def _vol(self, t):
+        g = self.scan.grid
+        if not (t.is_cuda and t.is_contiguous() and t.numel() == g.n_vox):
+            raise ValueError("volume must be a contiguous CUDA tensor with %d elements" % g.n_vox)
+        return t
+
+    def _proj(self, t):
+        n = self.scan.n_views * self.scan.det_rows * self.scan.det_cols
+        if not (t.is_cuda and t.is_contiguous() and t.numel() == n):
+            raise ValueError("projections must be a contiguous CUDA tensor with %d elements" % n)
+        return t
+
+    # -- entry points -------------------------------------------------------
+    def fp(self, vol, proj=None, view_begin=0, view_end=None, out_dtype=None, stream=None):
+        import torch
+        view_end = self.scan.n_views if view_end is None else view_end
+        self._vol(vol)
+        if proj is None:
+            proj = torch.zeros(self.scan.proj_shape, dtype=out_dtype or vol.dtype, device=vol.device)
+        self._proj(proj)
+        _check(self._L.cyl_fp(self.handle, C.c_void_p(vol.data_ptr()), _dtype_code(vol),
+                              C.c_void_p(proj.data_ptr()), _dtype_code(proj), view_begin, view_end,
+                              _stream_ptr(stream)), self._L)
+        return proj
+
+    def bp(self, proj, vol=None, view_begin=0, view_end=None, accumulate=False, out_dtype=None,
+           stream=None):
+        import torch
+        view_end = self.scan.n_views if view_end is None else view_end
+        self._proj(proj)
+        if vol is None:
+            vol = torch.empty(self.scan.grid.shape, dtype=out_dtype or proj.dtype, device=proj.device)
+            accumulate = False
+        self._vol(vol)
+        _check(self._L.cyl_bp(self.handle, C.c_void_p(proj.data_ptr()), _dtype_code(proj),
+                              C.c_void_p(vol.data_ptr()), _dtype_code(vol), view_begin, view_end,
+                              int(bool(accumulate)), _stream_ptr(stream)), self._L)
+        return vol
+
+    def row_sums(self, out=None, view_begin=0, view_end=None, stream=None):
+        import torch
+        view_end = self.scan.n_views if view_end is None else view_end
+        if out is None:
+            out = torch.zeros(self.scan.proj_shape, dtype=torch.float32, device="cuda:%d" % self.device)
+        self._proj(out)
+        if out.dtype != torch.float32:
+            raise TypeError("row sums are float32")
+        _check(self._L.cyl_row_sums(self.handle, C.c_void_p(out.data_ptr()), view_begin, view_end,
+                                    _stream_ptr(stream)), self._L)
+        return out
+
+    def sart_params(self, n_iter, lam=0.5, nonneg=False, view_order=None, start_iter=0,
+                    start_view=0):
+        prm = cyl_sart_params()
+        prm.n_iter, prm.lam, prm.nonneg = n_iter, lam, int(bool(nonneg))
+        prm.start_iter, prm.start_view = start_iter, start_view
+        keep = None
+        if view_order is not None:
+            keep = np.ascontiguousarray(view_order, dtype=np.int32).ravel()
+            if keep.size != self.scan.n_views:
+                raise ValueError("view_order needs exactly n_views = %d entries" % self.scan.n_views)
+            prm.view_order = keep.ctypes.data_as(C.POINTER(C.c_int32))
+        return prm, keep
+
+    def workspace_bytes(self, prm=None):
+        prm = prm or self.sart_params(1)[0]
+        return int(self._L.cyl_sart_workspace_bytes(self.handle, C.byref(prm)))
+
+    def sart(self, proj, vol, n_iter, lam=0.5, proj_weights=None, vox_weights=None, nonneg=False,
+             view_order=None, start_iter=0, start_view=0, workspace=None, stream=None):
+        """Weighted SART in place on `vol` (prior in, result out)."""
+        import torch
+        self._proj(proj)
+        self._vol(vol)
+        prm, keep = self.sart_params(n_iter, lam, nonneg, view_order, start_iter, start_view)
+        need = self.workspace_bytes(prm)
+        if workspace is None:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=vol.device)
+        pw = C.c_void_p(proj_weights.data_ptr()) if proj_weights is not None else None
+        vw = C.c_void_p(vox_weights.data_ptr()) if vox_weights is not None else None
+        if proj_weights is not None:
+            self._proj(proj_weights)
+        if vox_weights is not None:
+            self._vol(vox_weights)
+        _check(self._L.cyl_sart_run(
+            self.handle, C.byref(prm), C.c_void_p(proj.data_ptr()), _dtype_code(proj),
+            pw, _dtype_code(proj_weights) if proj_weights is not None else CYL_F32,
+            vw, _dtype_code(vox_weights) if vox_weights is not None else CYL_F32,
+            C.c_void_p(vol.data_ptr()), _dtype_code(vol), C.c_void_p(workspace.data_ptr()),
+            workspace.numel() * workspace.element_size(), _stream_ptr(stream)), self._L)
+        del keep
+        return vol
+
+    def sart_residual(self, view, proj, vol, workspace, proj_weights=None, stream=None):
+        """FP + residual epilogue of one view into `workspace` (FP32 rho)."""
+        self._proj(proj)
+        self._vol(vol)
+        pw = C.c_void_p(proj_weights.data_ptr()) if proj_weights is not None else None
+        _check(self._L.cyl_sart_residual(
+            self.handle, int(view), C.c_void_p(proj.data_ptr()), _dtype_code(proj), pw,
+            _dtype_code(proj_weights) if proj_weights is not None else CYL_F32,
+            C.c_void_p(vol.data_ptr()), _dtype_code(vol), C.c_void_p(workspace.data_ptr()),
+            workspace.numel() * workspace.element_size(), _stream_ptr(stream)), self._L)
+
+    def sart_update(self, view, vol, workspace, lam=0.5, vox_weights=None, nonneg=False,
+                    stream=None):
+        """BP + weighted update epilogue of one view, in place on `vol`."""
+        self._vol(vol)
+        vw = C.c_void_p(vox_weights.data_ptr()) if vox_weights is not None else None
+        _check(self._L.cyl_sart_update(
+            self.handle, int(view), float(lam), int(bool(nonneg)), vw,
+            _dtype_code(vox_weights) if vox_weights is not None else CYL_F32,
+            C.c_void_p(vol.data_ptr()), _dtype_code(vol), C.c_void_p(workspace.data_ptr()),
+            workspace.numel() * workspace.element_size(), _stream_ptr(stream)), self._L)

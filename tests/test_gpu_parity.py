@@ -1,0 +1,304 @@
+"""GPU parity of the HIP projectors and SART against the FP64 oracle.
+
+Every call goes through the C ABI (libcyl.so via the ctypes binding).  Bars:
+  * cyl_fp and cyl_bp: relative L2 <= 1e-5 against the oracle;
+  * adjoint <Ax, y> vs <x, A^T y> (FP64 dot products on the host): <= 1e-6;
+  * row sums (closed form, FP64 on the device): relative L2 <= 1e-7;
+  * SART iterates: relative L2 <= 1e-4 against the oracle's iterates;
+  * invariants exact (bitwise): fixed point, zero weights, resume, determinism.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_2005_11976_amd import inputs as I
+from tests.gpu_util import dev, host, max_rel, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+FP_TOL = 1e-5
+BP_TOL = 1e-5
+ADJ_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2005_11976_amd import cyl
+    cyl.lib()
+    return torch
+
+
+def _geom(scan):
+    from paper_2005_11976_amd import cyl
+    return cyl.Geometry(scan, 0)
+
+
+def _edge_scans():
+    out = []
+    views = I.circular_views(5, 40.0, 80.0, 1.1, 0.9, phi0=0.17)
+    R, T = I.pose_from(0.4, 0.3, 1.1, [0.7, -0.4, 0.5])
+    for name, grid in [
+        ("hollow", I.Grid(4, 8, 4, 1.5, 6.0, -2.0, 4.0, 0.3)),
+        ("ntheta1", I.Grid(3, 1, 3, 0.0, 6.0, -3.0, 3.0)),
+        ("ntheta2", I.Grid(3, 2, 2, 0.0, 6.0, -3.0, 3.0, 1.0)),
+        ("ntheta3", I.Grid(2, 3, 2, 0.0, 6.0, -3.0, 3.0)),
+        ("one_cell", I.Grid(1, 1, 1, 0.0, 6.0, -3.0, 3.0)),
+        ("ragged_blocks", I.Grid(7, 37, 19, 0.0, 6.0, -3.0, 3.0)),
+    ]:
+        out.append((name, I.Scan(grid, views, 8, 6, np.eye(3), np.zeros(3))))
+        out.append((name + "_posed", I.Scan(grid, views, 8, 6, R, T)))
+    # odd detector: the central column's rays pass exactly through the axis
+    g = I.Grid(6, 24, 6, 0.0, 6.0, -3.0, 3.0)
+    out.append(("through_axis", I.Scan(g, I.circular_views(4, 40.0, 80.0, 0.7), 9, 11,
+                                       np.eye(3), np.zeros(3))))
+    # ragged 8x8 tiles and a tilted object
+    R2, T2 = I.pose_from(1.0, math.radians(25.0), 0.2, [0.3, 0.1, -0.2])
+    out.append(("tilted25_ragged_tiles", I.Scan(I.Grid(10, 30, 8, 0.0, 6.0, -4.0, 4.0),
+                                                I.circular_views(3, 40.0, 80.0, 0.6), 21, 13, R2, T2)))
+    return out
+
+
+EDGE = _edge_scans()
+
+
+def _fp_bp_check(torch, scan, vb, ve, seed, label, fp_tol=FP_TOL, bp_tol=BP_TOL):
+    o = ref.Oracle(scan)
+    G = _geom(scan)
+    x = I.uniform_vector(scan.grid.n_vox, seed)
+    y = I.uniform_vector(scan.n_views * scan.det_rows * scan.det_cols, seed + 1)
+    say(label, "fp", scan.grid.shape, scan.proj_shape, (vb, ve))
+    xg = dev(x.astype(np.float32).reshape(scan.grid.shape))
+    q = host(G.fp(xg, view_begin=vb, view_end=ve))[vb:ve]
+    q_ref = o.fp(x.astype(np.float32).astype(np.float64), vb, ve)
+    e_fp = rel_l2(q, q_ref)
+    say(label, "bp")
+    yg = dev(y.astype(np.float32).reshape(scan.proj_shape))
+    b = host(G.bp(yg, view_begin=vb, view_end=ve))
+    y_ref = y.astype(np.float32).astype(np.float64).reshape(scan.proj_shape)[vb:ve]
+    b_ref = o.bp(y_ref, vb, ve)
+    e_bp = rel_l2(b, b_ref)
+    lhs = float(q.ravel() @ y_ref.ravel())
+    rhs = float(x.astype(np.float32).astype(np.float64) @ b.ravel())
+    e_adj = abs(lhs - rhs) / abs(lhs)
+    say(label, "fp %.2e (max %.2e) bp %.2e (max %.2e) adjoint %.2e" %
+        (e_fp, max_rel(q, q_ref), e_bp, max_rel(b, b_ref), e_adj))
+    assert e_fp <= fp_tol
+    assert e_bp <= bp_tol
+    assert e_adj <= ADJ_TOL
+    return q, b
+
+
+def test_fp_bp_tiny_all_views(torch_cuda):
+    cfg = I.config_tiny()
+    _fp_bp_check(torch_cuda, cfg["scan"], 0, cfg["scan"].n_views, 4001, "tiny")
+
+
+@pytest.mark.parametrize("case", EDGE, ids=[c[0] for c in EDGE])
+def test_fp_bp_edge_grids(torch_cuda, case):
+    name, scan = case
+    _fp_bp_check(torch_cuda, scan, 0, scan.n_views, 4011, name)
+
+
+def test_fp_bp_view_subrange_and_accumulate(torch_cuda):
+    scan = I.scaled_single(n_h=16, n_theta=48, n_r=12, n_views=6, det=40, posed_seed=2005)
+    G = _geom(scan)
+    o = ref.Oracle(scan)
+    x = I.uniform_vector(scan.grid.n_vox, 5).astype(np.float32)
+    xg = dev(x.reshape(scan.grid.shape))
+    say("subrange fp")
+    p = torch_cuda.full(scan.proj_shape, -7.0, device="cuda")
+    G.fp(xg, p, view_begin=2, view_end=4)
+    ph = host(p)
+    assert np.all(ph[:2] == -7.0) and np.all(ph[4:] == -7.0)
+    assert rel_l2(ph[2:4], o.fp(x.astype(np.float64), 2, 4)) <= FP_TOL
+    # empty range is a no-op
+    G.fp(xg, p, view_begin=3, view_end=3)
+    assert np.array_equal(host(p), ph)
+    say("subrange bp accumulate")
+    y = I.uniform_vector(scan.n_views * scan.det_rows * scan.det_cols, 6).astype(np.float32)
+    yg = dev(y.reshape(scan.proj_shape))
+    b = G.bp(yg, view_begin=0, view_end=3)
+    G.bp(yg, b, view_begin=3, view_end=6, accumulate=True)
+    ball = G.bp(yg)
+    assert rel_l2(host(b), host(ball)) <= 1e-6
+    assert rel_l2(host(ball), o.bp(y.astype(np.float64))) <= BP_TOL
+
+
+def test_row_sums_closed_form(torch_cuda):
+    from oracle import analytic
+    for scan in (I.config_tiny()["scan"], EDGE[1][1], EDGE[-1][1]):
+        say("row sums", scan.grid.shape)
+        G = _geom(scan)
+        o = ref.Oracle(scan)
+        Lg = host(G.row_sums())
+        Lr = o.row_sums()
+        assert rel_l2(Lg, Lr) <= 1e-7
+        a, e = o.ray_ends(0, 0, 0)
+        assert Lg[0, 0, 0] == pytest.approx(analytic.support_chord(scan.grid, a[None], e[None])[0],
+                                            rel=1e-6, abs=1e-6)
+
+
+def test_single_scan_full_size_fp_sampled(torch_cuda):
+    """256x720x128, 120 views: FP of the whole scan on the GPU, sampled rays
+    against the oracle (unposed and posed)."""
+    cfg = I.config_single()
+    for posed in (False, True):
+        scan = cfg["scan"]
+        if posed:
+            R, T, _ = I.random_pose(2002)
+            scan = I.Scan(scan.grid, scan.views, scan.det_rows, scan.det_cols, R, T)
+        say("single full fp posed=%s" % posed)
+        G = _geom(scan)
+        ph = I.industrial_phantom(scan.grid, cfg["seed"])
+        x = ph.truth.astype(np.float32)
+        q = host(G.fp(dev(x)))
+        rng = np.random.default_rng(99)
+        o = ref.Oracle(scan)
+        P = scan.det_rows * scan.det_cols
+        errs_num, errs_den = 0.0, 0.0
+        for k in rng.choice(scan.n_views, size=6, replace=False):
+            rays = rng.choice(P, size=500, replace=False)
+            qr, _ = o.fp_rays(x.astype(np.float64), rays, vb=int(k))
+            qg = q[int(k)].ravel()[rays]
+            errs_num += float(np.sum((qg - qr) ** 2))
+            errs_den += float(np.sum(qr ** 2))
+        e = math.sqrt(errs_num / errs_den)
+        say("single full fp posed=%s sampled rel L2 %.2e" % (posed, e))
+        assert e <= FP_TOL
+
+
+def test_single_scan_full_size_bp_one_view(torch_cuda):
+    """256x720x128: BP of one full 512x512 view against the oracle, plus the
+    adjoint identity on that view."""
+    cfg = I.config_single()
+    R, T, _ = I.random_pose(2002)
+    scan = I.Scan(cfg["scan"].grid, cfg["scan"].views, 512, 512, R, T)
+    _fp_bp_check(torch_cuda, scan, 17, 18, 4021, "single posed view 17")
+
+
+def test_posed_large_bp_one_view(torch_cuda):
+    """512x1440x256 posed scan, 1024x768 detector: one view FP and BP."""
+    cfg = I.config_posed()
+    _fp_bp_check(torch_cuda, cfg["scan"], 11, 12, 4031, "posed large view 11", bp_tol=1.5e-5)
+
+
+# ------------------------------------------------------------------ SART
+
+def _sart_pair(torch, scan, ph, n_iter, weighted, from_prior, lam=0.5, label=""):
+    o = ref.Oracle(scan)
+    G = _geom(scan)
+    p = o.fp(ph.truth)
+    mu0 = ph.prior if from_prior else np.zeros(scan.grid.shape)
+    vw = ph.weights if weighted else None
+    errs = []
+    vol = dev(mu0.astype(np.float32))
+    pg = dev(p.astype(np.float32))
+    vwg = dev(vw.astype(np.float32)) if vw is not None else None
+    mu_ref = mu0.copy()
+    for it in range(n_iter):
+        say(label, "sart iteration", it)
+        G.sart(pg, vol, it + 1, lam, vox_weights=vwg, start_iter=it)
+        mu_ref, _ = o.sart(p.astype(np.float32).astype(np.float64), mu_ref, it + 1, lam,
+                           vox_weights=vw, start_iter=it)
+        errs.append(rel_l2(host(vol), mu_ref))
+    say(label, "per-iteration rel L2", " ".join("%.2e" % e for e in errs))
+    return errs, host(vol), mu_ref
+
+
+def test_sart_tiny_ten_iterations(torch_cuda):
+    cfg = I.config_tiny()
+    scan = cfg["scan"]
+    ph = I.tiny_phantom(scan.grid, cfg["seed"])
+    errs, got, want = _sart_pair(torch_cuda, scan, ph, 10, False, False, label="tiny")
+    assert max(errs) <= 1e-4
+
+
+def test_sart_weighted_prior_posed_scaled(torch_cuda):
+    scan = I.scaled_single(n_h=24, n_theta=72, n_r=16, n_views=16, det=48, posed_seed=2006)
+    ph = I.industrial_phantom(scan.grid, 1002, n_annuli=5, n_incl=6)
+    errs, got, want = _sart_pair(torch_cuda, scan, ph, 3, True, True, label="scaled weighted")
+    assert max(errs) <= 1e-4
+
+
+def test_sart_invariants_bitwise(torch_cuda):
+    torch = torch_cuda
+    scan = I.scaled_single(n_h=16, n_theta=48, n_r=12, n_views=8, det=40, posed_seed=2007)
+    ph = I.industrial_phantom(scan.grid, 55, n_annuli=4, n_incl=3)
+    G = _geom(scan)
+    truth = dev(ph.truth.astype(np.float32))
+    say("invariants: fixed point")
+    p = G.fp(truth)
+    vol = truth.clone()
+    G.sart(p, vol, 2, 0.5, vox_weights=dev(ph.weights.astype(np.float32)))
+    assert torch.equal(vol, truth)
+    say("invariants: zero weights")
+    w = ph.weights.astype(np.float32).copy()
+    w[:, :, :3] = 0.0
+    prior = dev(ph.prior.astype(np.float32) * 0.5)
+    vol = prior.clone()
+    G.sart(p, vol, 1, 0.5, vox_weights=dev(w))
+    assert torch.equal(vol[:, :, :3], prior[:, :, :3])
+    assert not torch.equal(vol[:, :, 3:], prior[:, :, 3:])
+    say("invariants: resume and determinism")
+    a = prior.clone()
+    G.sart(p, a, 4, 0.5)
+    b = prior.clone()
+    G.sart(p, b, 2, 0.5)
+    G.sart(p, b, 4, 0.5, start_iter=2)
+    assert torch.equal(a, b)
+    e1 = prior.clone()
+    G.sart(p, e1, 1, 0.5)
+    e2 = prior.clone()
+    G.sart(p, e2, 1, 0.5, view_order=np.arange(scan.n_views))
+    assert torch.equal(e1, e2)
+    e3 = prior.clone()
+    G.sart(p, e3, 1, 0.5, view_order=np.arange(scan.n_views)[::-1].copy())
+    assert not torch.equal(e1, e3)
+    say("invariants: linear in lambda (first view)")
+    one = I.Scan(scan.grid, scan.views[:1], scan.det_rows, scan.det_cols, scan.R, scan.T)
+    G1 = _geom(one)
+    m1 = prior.clone()
+    G1.sart(p[:1].contiguous(), m1, 1, 0.25)
+    m2 = prior.clone()
+    G1.sart(p[:1].contiguous(), m2, 1, 0.5)
+    d1 = host(m1) - host(prior)
+    d2 = host(m2) - host(prior)
+    assert rel_l2(d2, 2 * d1) <= 1e-5
+
+
+def test_sart_mid_sweep_resume_bitwise(torch_cuda):
+    torch = torch_cuda
+    scan = I.scaled_single(n_h=16, n_theta=48, n_r=12, n_views=8, det=40)
+    ph = I.industrial_phantom(scan.grid, 56, n_annuli=4, n_incl=3)
+    G = _geom(scan)
+    p = G.fp(dev(ph.truth.astype(np.float32)))
+    prior = dev(ph.prior.astype(np.float32))
+    full = prior.clone()
+    G.sart(p, full, 2, 0.5)
+    # 1 iteration + 3 views, then resume from (1, 3)
+    part = prior.clone()
+    G.sart(p, part, 1, 0.5)
+    first3 = I.Scan(scan.grid, scan.views[:3], scan.det_rows, scan.det_cols, scan.R, scan.T)
+    G3 = _geom(first3)
+    G3.sart(p[:3].contiguous(), part, 1, 0.5)
+    G.sart(p, part, 2, 0.5, start_iter=1, start_view=3)
+    assert torch.equal(full, part)
+
+
+def test_sart_rejects_bad_arguments(torch_cuda):
+    from paper_2005_11976_amd import cyl
+    scan = I.scaled_single(n_h=8, n_theta=24, n_r=6, n_views=4, det=20)
+    G = _geom(scan)
+    vol = dev(np.zeros(scan.grid.shape, np.float32))
+    p = dev(np.zeros(scan.proj_shape, np.float32))
+    tiny_ws = torch_cuda.empty(16, dtype=torch_cuda.uint8, device="cuda")
+    with pytest.raises(cyl.CylError, match="workspace"):
+        G.sart(p, vol, 1, 0.5, workspace=tiny_ws)
+    with pytest.raises(cyl.CylError, match="view_order"):
+        G.sart(p, vol, 1, 0.5, view_order=np.array([0, 1, 2, 9]))
+    with pytest.raises(cyl.CylError, match="view range"):
+        G.fp(vol, p, view_begin=2, view_end=9)
