@@ -136,6 +136,12 @@ extern "C" int cyl_geom_create(const cyl_grid *grid, const cyl_traj *traj, const
         set_error("cyl_geom_create: R is a reflection (det < 0)");
         return CYL_EINVAL;
     }
+    const size_t table_bytes = 8 * ((size_t)(g.n_r + 1) + (g.n_h + 1) + (g.n_theta + 1));
+    if (table_bytes > kMaxLds / 2) {
+        set_error("cyl_geom_create: grid tables of %zu bytes exceed the %zu-byte LDS budget "
+                  "(n_r + n_h + n_theta must stay below %zu)", table_bytes, kMaxLds / 2, kMaxLds / 16 - 3);
+        return CYL_EUNSUPPORTED;
+    }
     int ndev = 0;
     // per-view object-frame geometry (Eq. 1, FP64)
     const int nv = traj->n_views, H = traj->det_rows, W = traj->det_cols;
@@ -256,6 +262,9 @@ extern "C" int cyl_geom_create(const cyl_grid *grid, const cyl_traj *traj, const
     d.dh = (float)dh;
     d.theta0 = (float)g.theta0;
     d.dtheta = (float)dth;
+    d.inv_dr = (float)(1.0 / dr);
+    d.inv_dh = (float)(1.0 / dh);
+    d.inv_dtheta = (float)(1.0 / dth);
     d.r_min_d = g.r_min;
     d.r_max_d = g.r_max;
     d.h_min_d = g.h_min;
@@ -272,6 +281,15 @@ extern "C" int cyl_geom_create(const cyl_grid *grid, const cyl_traj *traj, const
     if (bt < 1) bt = 1;
     if (bt > 16) bt = 16;
     d.bt = bt;
+    // shrink the block until 4 accumulator blocks (c and n) fit beside the tables
+    while ((size_t)4 * 2 * 4 * (d.bh * d.bt * d.br + 1) + table_bytes > kMaxLds) {
+        if (d.br > 4)
+            d.br /= 2;
+        else if (d.bt > 1)
+            d.bt = (d.bt + 1) / 2;
+        else
+            d.bh = 1;
+    }
     d.nbh = (g.n_h + d.bh - 1) / d.bh;
     d.nbt = (g.n_theta + d.bt - 1) / d.bt;
     d.nbr = (g.n_r + d.br - 1) / d.br;

@@ -26,6 +26,7 @@ struct GeomDev {
     int32_t n_h, n_theta, n_r;
     int32_t n_views, rows, cols;
     float r_min, dr, h_min, dh, theta0, dtheta;
+    float inv_dr, inv_dh, inv_dtheta;
     double r_min_d, r_max_d, h_min_d, h_max_d;
     const float2 *r_tab;   // n_r + 1 shell radii as (hi, lo) float pairs
     const float2 *h_tab;   // n_h + 1 axial planes as (hi, lo)
@@ -37,7 +38,8 @@ struct GeomDev {
     int32_t nbh, nbt, nbr;
 };
 
-constexpr int kBlockCells = 1024;  // LDS cells per back-projection block (per wave)
+constexpr int kBlockCells = 1024;    // max cells per back-projection block (one block per wave)
+constexpr size_t kMaxLds = 65536;    // LDS per workgroup: grid tables + 4 block accumulators
 
 }  // namespace cyl
 

@@ -73,6 +73,32 @@ __device__ __forceinline__ float ld_any(const void *p, int dt, size_t i) {
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// ------------------------------------------------------------ grid tables
+
+// Grid tables as seen by a kernel (staged in LDS by every workgroup).
+struct Tabs {
+    const float2 *r;   // n_r + 1 shell radii (hi, lo)
+    const float2 *h;   // n_h + 1 axial planes (hi, lo)
+    const float2 *cs;  // n_theta + 1 sector edges (cos, sin)
+};
+
+__device__ __forceinline__ size_t table_floats2(const GeomDev &g) {
+    return (size_t)(g.n_r + 1) + (g.n_h + 1) + (g.n_theta + 1);
+}
+
+// Cooperative copy of the grid tables into LDS; the caller synchronises.
+__device__ __forceinline__ Tabs stage_tables(const GeomDev &g, float2 *smem) {
+    const int nr = g.n_r + 1, nh = g.n_h + 1, nc = g.n_theta + 1;
+    for (int i = threadIdx.x; i < nr; i += blockDim.x) smem[i] = g.r_tab[i];
+    for (int i = threadIdx.x; i < nh; i += blockDim.x) smem[nr + i] = g.h_tab[i];
+    for (int i = threadIdx.x; i < nc; i += blockDim.x) smem[nr + nh + i] = g.cs_tab[i];
+    Tabs T;
+    T.r = smem;
+    T.h = smem + nr;
+    T.cs = smem + nr + nh;
+    return T;
+}
+
 // ------------------------------------------------------------ per-ray set-up
 
 enum : int { RAY_HIT = 1, RAY_AXIAL = 2, RAY_THRU = 4 };
@@ -98,7 +124,7 @@ __device__ __forceinline__ int sector_of(const GeomDev &g, float x, float y) {
     const float two_pi = 6.28318530717958647692f;
     float th = atan2f(y, x) - g.theta0;
     th -= two_pi * floorf(th * (1.0f / two_pi));
-    int it = (int)floorf(th / g.dtheta);
+    int it = (int)floorf(th * g.inv_dtheta);
     it = it < 0 ? 0 : it;
     return it >= g.n_theta ? g.n_theta - 1 : it;
 }
@@ -131,45 +157,46 @@ struct EdgeX {
     bool on_edge;
 };
 
-__device__ __forceinline__ EdgeX edge_cross(const GeomDev &g, const ViewDev &V, const RayF &r, int b) {
+__device__ __forceinline__ EdgeX edge_cross(const GeomDev &g, const Tabs &T, const ViewDev &V, const RayF &r,
+                                            int b) {
     EdgeX x;
-    const float2 cs = g.cs_tab[b];
+    const float2 cs = T.cs[b];
     x.nc = cs.x * r.cy - cs.y * r.cx;
     x.ne = cs.x * r.ey - cs.y * r.ex;
-    if (fabsf(x.ne) >= kEdgeTau) {
-        x.on_edge = (cs.x * r.cx + cs.y * r.cy) > 0.0f;
-        x.s = -x.nc * frcp(x.ne);
-        return x;
+    x.on_edge = (cs.x * r.cx + cs.y * r.cy) > 0.0f;
+    x.s = -x.nc * frcp(x.ne);
+    if (fabsf(x.ne) < kEdgeTau) {
+        const double2 c = g.cs64[b];
+        const double nd = c.x * r.dyd - c.y * r.dxd;
+        const double na = c.x * V.a[1] - c.y * V.a[0];
+        x.ne = (float)nd;
+        x.nc = (float)na;
+        if (nd == 0.0) {
+            x.on_edge = false;
+            x.s = CYL_INF;
+        } else {
+            const double t = -na / nd;
+            const double px = fma(t, r.dxd, V.a[0]), py = fma(t, r.dyd, V.a[1]);
+            x.on_edge = (c.x * px + c.y * py) > 0.0;
+            x.s = (float)((t - r.tcd) * (double)r.len);
+        }
     }
-    const double2 c = g.cs64[b];
-    const double nd = c.x * r.dyd - c.y * r.dxd;
-    const double na = c.x * V.a[1] - c.y * V.a[0];
-    x.ne = (float)nd;
-    x.nc = (float)na;
-    if (nd == 0.0) {
-        x.on_edge = false;
-        x.s = CYL_INF;
-        return x;
-    }
-    const double t = -na / nd;
-    const double px = fma(t, r.dxd, V.a[0]), py = fma(t, r.dyd, V.a[1]);
-    x.on_edge = (c.x * px + c.y * py) > 0.0;
-    x.s = (float)((t - r.tcd) * (double)r.len);
     return x;
 }
 
-// Cheap mostly-FP32 ray set-up shared by every kernel.  FP64 is used for the
-// pixel direction, the closest-approach parameter (one FP64 Newton step on an
-// FP32 quotient), the closest point and its distance.
-__device__ __forceinline__ void ray_geom(const GeomDev &g, const ViewDev &V, int u, int v, RayF &r,
-                                         double &tc_out, double &dx, double &dy, double &dz) {
+// Mostly-FP32 ray set-up shared by every kernel.  FP64 is used for the pixel
+// direction, the closest-approach parameter (one FP64 Newton step on an FP32
+// quotient), the closest point and its distance.
+__device__ __forceinline__ void ray_geom(const GeomDev &g, const Tabs &T, const ViewDev &V, int u, int v,
+                                         RayF &r, double &dzo) {
     const double fu = (double)u, fv = (double)v;
-    dx = fma(fv, V.V[0], fma(fu, V.U[0], V.d0[0]));
-    dy = fma(fv, V.V[1], fma(fu, V.U[1], V.d0[1]));
-    dz = fma(fv, V.V[2], fma(fu, V.U[2], V.d0[2]));
+    const double dx = fma(fv, V.V[0], fma(fu, V.U[0], V.d0[0]));
+    const double dy = fma(fv, V.V[1], fma(fu, V.U[1], V.d0[1]));
+    const double dz = fma(fv, V.V[2], fma(fu, V.U[2], V.d0[2]));
+    dzo = dz;
     const double A = fma(dx, dx, dy * dy);
     const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
-    const float len = fsqrt(fma(fdx, fdx, fma(fdy, fdy, fdz * fdz)));
+    const float len = fsqrt(fmaf(fdx, fdx, fmaf(fdy, fdy, fdz * fdz)));
     const float il = frcp(len);
     r.ex = fdx * il;
     r.ey = fdy * il;
@@ -178,6 +205,7 @@ __device__ __forceinline__ void ray_geom(const GeomDev &g, const ViewDev &V, int
     r.len = len;
     r.dxd = dx;
     r.dyd = dy;
+    r.it_in = r.it_out = 0;
     double tc;
     if (A > 0.0) {
         const double B = fma(V.a[0], dx, V.a[1] * dy);
@@ -194,6 +222,7 @@ __device__ __forceinline__ void ray_geom(const GeomDev &g, const ViewDev &V, int
         tc = tc < 0.0 ? 0.0 : (tc > 1.0 ? 1.0 : tc);
         r.inv_k = CYL_INF;
     }
+    r.tcd = tc;
     const double cxd = fma(tc, dx, V.a[0]);
     const double cyd = fma(tc, dy, V.a[1]);
     const double b2 = fma(cxd, cxd, cyd * cyd);
@@ -206,14 +235,11 @@ __device__ __forceinline__ void ray_geom(const GeomDev &g, const ViewDev &V, int
     r.zc = (float)zcd;
     r.zclo = (float)(zcd - (double)r.zc);
     r.inv_ez = (fdz != 0.0f) ? len / fdz : CYL_INF;
-    tc_out = tc;
-    r.tcd = tc;
-    const float ftc = (float)tc;
-    float s0 = -ftc * len, s1 = (float)(1.0 - tc) * len;
+    float s0 = -(float)tc * len, s1 = (float)(1.0 - tc) * len;
     // support interval with the same crossing formulas as the traversal
     bool hit = true;
     if (!(r.flags & RAY_AXIAL)) {
-        float w = shell_w(g.r_tab[g.n_r], r);
+        const float w = shell_w(T.r[g.n_r], r);
         if (w < 0.0f) hit = false;
         s0 = fmaxf(s0, -w);
         s1 = fminf(s1, w);
@@ -223,16 +249,15 @@ __device__ __forceinline__ void ray_geom(const GeomDev &g, const ViewDev &V, int
             r.it_out = sector_of(g, r.ex, r.ey);
         }
     } else {
-        float2 rt = g.r_tab[g.n_r];
+        const float2 rt = T.r[g.n_r];
         if (!((rt.x - r.b) + (rt.y - r.blo) > 0.0f)) hit = false;
     }
     if (fdz != 0.0f) {
-        float t1 = plane_s(g.h_tab[0], r), t2 = plane_s(g.h_tab[g.n_h], r);
+        const float t1 = plane_s(T.h[0], r), t2 = plane_s(T.h[g.n_h], r);
         s0 = fmaxf(s0, fminf(t1, t2));
         s1 = fminf(s1, fmaxf(t1, t2));
-    } else {
-        float2 lo = g.h_tab[0], hi = g.h_tab[g.n_h];
-        if (!(r.zc >= lo.x && r.zc < hi.x)) hit = false;
+    } else if (!(r.zc >= T.h[0].x && r.zc < T.h[g.n_h].x)) {
+        hit = false;
     }
     r.s_in = s0;
     r.s_out = s1;
@@ -240,9 +265,9 @@ __device__ __forceinline__ void ray_geom(const GeomDev &g, const ViewDev &V, int
 }
 
 // Closed-form row sum L_j in FP64: length inside the support minus the hole.
-__device__ __forceinline__ float row_sum_fp64(const GeomDev &g, const ViewDev &V, const RayF &r,
-                                              double tc, double dx, double dy, double dz) {
+__device__ __forceinline__ float row_sum_fp64(const GeomDev &g, const ViewDev &V, const RayF &r, double dz) {
     if (!(r.flags & RAY_HIT)) return 0.0f;
+    const double dx = r.dxd, dy = r.dyd, tc = r.tcd;
     const double A = fma(dx, dx, dy * dy);
     const double len = sqrt(A + dz * dz);
     double lo = -tc * len, hi = (1.0 - tc) * len;
@@ -252,7 +277,7 @@ __device__ __forceinline__ float row_sum_fp64(const GeomDev &g, const ViewDev &V
     if (A > 0.0) {
         ik = len / sqrt(A);
         if (!(b < g.r_max_d)) return 0.0f;
-        double w = sqrt((g.r_max_d - b) * (g.r_max_d + b)) * ik;
+        const double w = sqrt((g.r_max_d - b) * (g.r_max_d + b)) * ik;
         lo = fmax(lo, -w);
         hi = fmin(hi, w);
     } else if (!(b < g.r_max_d)) {
@@ -260,7 +285,7 @@ __device__ __forceinline__ float row_sum_fp64(const GeomDev &g, const ViewDev &V
     }
     if (dz != 0.0) {
         const double zc = fma(tc, dz, V.a[2]);
-        double t1 = (g.h_min_d - zc) * len / dz, t2 = (g.h_max_d - zc) * len / dz;
+        const double t1 = (g.h_min_d - zc) * len / dz, t2 = (g.h_max_d - zc) * len / dz;
         lo = fmax(lo, fmin(t1, t2));
         hi = fmin(hi, fmax(t1, t2));
     }
@@ -268,7 +293,7 @@ __device__ __forceinline__ float row_sum_fp64(const GeomDev &g, const ViewDev &V
     double L = hi - lo;
     if (g.r_min_d > 0.0 && b < g.r_min_d) {
         if (A > 0.0) {
-            double w = sqrt((g.r_min_d - b) * (g.r_min_d + b)) * ik;
+            const double w = sqrt((g.r_min_d - b) * (g.r_min_d + b)) * ik;
             L -= fmax(0.0, fmin(hi, w) - fmax(lo, -w));
         } else {
             L = 0.0;
@@ -278,14 +303,13 @@ __device__ __forceinline__ float row_sum_fp64(const GeomDev &g, const ViewDev &V
 }
 
 // Cell at parameter s (indices clamped into the grid; ir = -1 inside the hole).
-__device__ __forceinline__ void cell_at(const GeomDev &g, const RayF &r, float s, int &ih, int &it,
-                                        int &ir) {
+__device__ __forceinline__ void cell_at(const GeomDev &g, const RayF &r, float s, int &ih, int &it, int &ir) {
     const float x = fmaf(s, r.ex, r.cx), y = fmaf(s, r.ey, r.cy), z = fmaf(s, r.ez, r.zc);
     const float q = s / r.inv_k;
     const float rr = fsqrt(fmaf(r.b, r.b, q * q));
-    int h = (int)floorf((z - g.h_min) / g.dh);
+    const int h = (int)floorf((z - g.h_min) * g.inv_dh);
     ih = h < 0 ? 0 : (h >= g.n_h ? g.n_h - 1 : h);
-    int ri = (int)floorf((rr - g.r_min) / g.dr);
+    const int ri = (int)floorf((rr - g.r_min) * g.inv_dr);
     ir = ri < -1 ? -1 : (ri >= g.n_r ? g.n_r - 1 : ri);
     if (r.flags & RAY_THRU)
         it = (s < 0.0f) ? r.it_in : r.it_out;
@@ -295,128 +319,154 @@ __device__ __forceinline__ void cell_at(const GeomDev &g, const RayF &r, float s
 
 // ------------------------------------------------------------ traversal
 
-struct Walker {
-    int dir_h, dir_t;
-    bool r_in;
-    float s_z, s_r, s_t;
+// Next crossing of each family after s, for the current cell.
+__device__ __forceinline__ float next_z(const Tabs &T, const RayF &r, int dir_h, int ih, float s) {
+    const float sz = plane_s(T.h[ih + (dir_h > 0 ? 1 : 0)], r);
+    return dir_h != 0 ? fmaxf(sz, s) : CYL_INF;
+}
 
-    __device__ __forceinline__ float next_z(const GeomDev &g, const RayF &r, int ih, float s) const {
-        if (dir_h == 0) return CYL_INF;
-        return fmaxf(plane_s(g.h_tab[dir_h > 0 ? ih + 1 : ih], r), s);
-    }
-    __device__ __forceinline__ float next_r(const GeomDev &g, const RayF &r, int ir, float s) {
-        if (r.flags & RAY_AXIAL) return CYL_INF;
-        if (s < 0.0f && ir >= 0) {
-            float w = shell_w(g.r_tab[ir], r);
-            if (w >= 0.0f) {
-                r_in = true;
-                return fmaxf(-w, s);
-            }
-        }
-        r_in = false;
-        float w = shell_w(g.r_tab[ir + 1], r);
-        return w < 0.0f ? CYL_INF : fmaxf(w, s);
-    }
-    __device__ __forceinline__ float next_t(const GeomDev &g, const ViewDev &V, const RayF &r, int it,
-                                            float s) const {
-        if (r.flags & RAY_THRU) return s < 0.0f ? 0.0f : CYL_INF;
-        if (dir_t == 0) return CYL_INF;
-        // an edge-half-line meeting behind s means the start cell was one
-        // sector short (rounding at entry): cross it at once
-        const EdgeX x = edge_cross(g, V, r, dir_t > 0 ? it + 1 : it);
-        return x.on_edge ? fmaxf(x.s, s) : CYL_INF;
-    }
-};
+// Shell crossing: inward through the lower radius while before the closest
+// approach and the ray reaches it, else outward through the upper radius.
+__device__ __forceinline__ float next_r(const Tabs &T, const RayF &r, int ir, float s, int &r_dir) {
+    const float2 rl = T.r[ir < 0 ? 0 : ir], ru = T.r[ir + 1];
+    const float dl = (rl.x - r.b) + (rl.y - r.blo);
+    const float du = (ru.x - r.b) + (ru.y - r.blo);
+    const bool inward = (s < 0.0f) && (ir >= 0) && (dl > 0.0f);
+    const float d = inward ? dl : du;
+    const float w = fsqrt(fmaxf(d, 0.0f) * ((inward ? rl.x : ru.x) + r.b)) * r.inv_k;
+    r_dir = inward ? -1 : 1;
+    return (r.flags & RAY_AXIAL) ? CYL_INF : fmaxf(inward ? -w : w, s);
+}
+
+__device__ __forceinline__ float next_t(const GeomDev &g, const Tabs &T, const ViewDev &V, const RayF &r, int dir_t,
+                                        int it, float s) {
+    if (r.flags & RAY_THRU) return s < 0.0f ? 0.0f : CYL_INF;
+    // an edge-half-line meeting behind s means the start cell was one sector
+    // short (rounding at entry): cross it at once
+    const EdgeX x = edge_cross(g, T, V, r, it + (dir_t > 0 ? 1 : 0));
+    return (dir_t != 0 && x.on_edge) ? fmaxf(x.s, s) : CYL_INF;
+}
 
 // Walk the ray from s to s_end starting in cell (ih, it, ir) and call
-// visit(ih, it, ir, length) for every piece with ir >= 0.
+// visit(ih, it, ir, length) for every piece (length 0 allowed; ir = -1 is the
+// hole).  Every step computes all three next-crossing candidates with selects
+// (no divergent branches but the rare FP64 edge case); the visitor is called
+// before the index updates so a gather it issues overlaps them.
 template <class Visit>
-__device__ __forceinline__ void traverse(const GeomDev &g, const ViewDev &V, const RayF &r, float s,
+__device__ __forceinline__ void traverse(const GeomDev &g, const Tabs &T, const ViewDev &V, const RayF &r, float s,
                                          const float s_end, int ih, int it, int ir, Visit &visit) {
-    Walker w;
-    w.dir_h = r.ez > 0.0f ? 1 : (r.ez < 0.0f ? -1 : 0);
+    const int dir_h = r.ez > 0.0f ? 1 : (r.ez < 0.0f ? -1 : 0);
     const float cross = r.cx * r.ey - r.cy * r.ex;
-    w.dir_t = (g.n_theta == 1 || (r.flags & (RAY_AXIAL | RAY_THRU))) ? 0
-              : (cross > 0.0f ? 1 : (cross < 0.0f ? -1 : 0));
-    w.r_in = false;
-    w.s_z = w.next_z(g, r, ih, s);
-    w.s_r = w.next_r(g, r, ir, s);
-    w.s_t = (g.n_theta == 1) ? CYL_INF : w.next_t(g, V, r, it, s);
+    const int dir_t = (g.n_theta == 1 || (r.flags & (RAY_AXIAL | RAY_THRU))) ? 0
+                      : (cross > 0.0f ? 1 : (cross < 0.0f ? -1 : 0));
+    int r_dir;
+    float s_z = next_z(T, r, dir_h, ih, s);
+    float s_r = next_r(T, r, ir, s, r_dir);
+    float s_t = (g.n_theta == 1) ? CYL_INF : next_t(g, T, V, r, dir_t, it, s);
     const int max_steps = 2 * g.n_r + g.n_theta + g.n_h + 8;
     for (int n = 0; n < max_steps; ++n) {
-        const float sn = fminf(fminf(w.s_z, w.s_r), fminf(w.s_t, s_end));
-        if (ir >= 0) visit(ih, it, ir, sn - s);
+        const float sn = fminf(fminf(s_z, s_r), fminf(s_t, s_end));
+        visit(ih, it, ir, sn - s);
         s = sn;
-        if (!(sn < s_end)) break;
-        if (sn == w.s_z) {
-            ih += w.dir_h;
-            if ((unsigned)ih >= (unsigned)g.n_h) break;
-            w.s_z = w.next_z(g, r, ih, s);
-        } else if (sn == w.s_r) {
-            ir += w.r_in ? -1 : 1;
-            if (ir >= g.n_r) break;
-            w.s_r = w.next_r(g, r, ir, s);
-        } else {
-            if (r.flags & RAY_THRU) {
-                it = r.it_out;
-            } else {
-                it += w.dir_t;
-                it = it < 0 ? it + g.n_theta : (it >= g.n_theta ? it - g.n_theta : it);
-            }
-            w.s_t = w.next_t(g, V, r, it, s);
-        }
+        const bool ev_z = (sn == s_z);
+        const bool ev_r = !ev_z && (sn == s_r);
+        const bool ev_t = !ev_z && !ev_r;
+        ih += ev_z ? dir_h : 0;
+        ir += ev_r ? r_dir : 0;
+        int itn = it + (ev_t ? dir_t : 0);
+        itn = itn < 0 ? itn + g.n_theta : (itn >= g.n_theta ? itn - g.n_theta : itn);
+        it = (ev_t && (r.flags & RAY_THRU)) ? r.it_out : itn;
+        if (!(sn < s_end) || (unsigned)ih >= (unsigned)g.n_h || ir >= g.n_r) break;
+        int rd;
+        const float nz = next_z(T, r, dir_h, ih, s);
+        const float nr = next_r(T, r, ir, s, rd);
+        const float nt = next_t(g, T, V, r, dir_t, it, s);
+        s_z = ev_z ? nz : s_z;
+        s_r = ev_r ? nr : s_r;
+        r_dir = ev_r ? rd : r_dir;
+        s_t = ev_t ? nt : s_t;
     }
 }
 
 // ------------------------------------------------------------ forward projection
 
-// 8 x 8 pixel tile per wave; blockIdx.y = view offset.
+// Partial forward projection of piece `piece` of `npieces` equal parameter
+// ranges of ray (u, v): each piece starts from its own cell so the pieces of
+// one ray can run on neighbouring lanes.
+template <int VT>
+__device__ __forceinline__ float fp_piece(const GeomDev &g, const Tabs &T, const ViewDev &V, const RayF &r,
+                                          const void *__restrict__ vol, int piece, int npieces) {
+    float acc = 0.0f;
+    if (!(r.flags & RAY_HIT)) return acc;
+    const float span = (r.s_out - r.s_in) / (float)npieces;
+    const float a0 = piece == 0 ? r.s_in : fmaf((float)piece, span, r.s_in);
+    const float a1 = piece == npieces - 1 ? r.s_out : fmaf((float)(piece + 1), span, r.s_in);
+    if (!(a1 > a0)) return acc;
+    int ih, it, ir;
+    cell_at(g, r, a0, ih, it, ir);
+    const int nt = g.n_theta, nr = g.n_r;
+    auto visit = [&](int h, int t, int q, float len) {
+        const int idx = (h * nt + t) * nr + (q < 0 ? 0 : q);
+        const float val = Store<VT>::ld(vol, (size_t)idx);
+        acc = fmaf(q < 0 ? 0.0f : len, val, acc);
+    };
+    traverse(g, T, V, r, a0, a1, ih, it, ir, visit);
+    return acc;
+}
+
+// Workgroup of 256 lanes = a 16-wide pixel tile x NSPLIT pieces per ray;
+// blockIdx.y = view offset.  Tiles are spread so that each XCD (blocks are
+// dealt round-robin to the 8 XCDs) works on a contiguous band of rows.
 template <int VT, int PT, bool SART>
-__global__ __launch_bounds__(64) void fp_kernel(GeomDev g, const void *__restrict__ vol,
-                                                void *__restrict__ proj, int view_begin,
-                                                const void *__restrict__ pw, int pwt,
-                                                float *__restrict__ rho) {
+__global__ __launch_bounds__(256) void fp_kernel(GeomDev g, const void *__restrict__ vol, void *__restrict__ proj,
+                                                 int view_begin, int nsplit, const void *__restrict__ pw, int pwt,
+                                                 float *__restrict__ rho) {
+    extern __shared__ float2 smem[];
+    const Tabs T = stage_tables(g, smem);
+    __syncthreads();
     const int k = view_begin + blockIdx.y;
-    const int tiles_u = (g.cols + 7) >> 3;
-    const int u = (blockIdx.x % tiles_u) * 8 + (threadIdx.x & 7);
-    const int v = (blockIdx.x / tiles_u) * 8 + (threadIdx.x >> 3);
-    if (u >= g.cols || v >= g.rows) return;
+    const int tw = 16, th = 256 / nsplit / 16;
+    const int tiles_u = (g.cols + tw - 1) / tw;
+    const int ntiles = tiles_u * ((g.rows + th - 1) / th);
+    int tile = blockIdx.x;
+    if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
+    const int p = threadIdx.x / nsplit, piece = threadIdx.x % nsplit;
+    const int u = (tile % tiles_u) * tw + (p % tw);
+    const int v = (tile / tiles_u) * th + (p / tw);
+    const bool live = u < g.cols && v < g.rows;
     const ViewDev &V = g.views[k];
     RayF r;
-    double tc, dx, dy, dz;
-    ray_geom(g, V, u, v, r, tc, dx, dy, dz);
-    float acc = 0.0f;
-    if (r.flags & RAY_HIT) {
-        int ih, it, ir;
-        cell_at(g, r, r.s_in, ih, it, ir);
-        const int nt = g.n_theta, nr = g.n_r;
-        auto visit = [&](int h, int t, int q, float len) {
-            acc = fmaf(len, Store<VT>::ld(vol, (size_t)((h * nt + t) * nr + q)), acc);
-        };
-        traverse(g, V, r, r.s_in, r.s_out, ih, it, ir, visit);
-    }
+    double dz;
+    ray_geom(g, T, V, live ? u : 0, live ? v : 0, r, dz);
+    if (!live) r.flags = 0;
+    float acc = fp_piece<VT>(g, T, V, r, vol, piece, nsplit);
+    for (int o = 1; o < nsplit; o <<= 1) acc += __shfl_xor(acc, o);
+    if (!live || piece != 0) return;
     const size_t j = ((size_t)k * g.rows + v) * g.cols + u;
     if (!SART) {
         Store<PT>::st(proj, j, acc);
     } else {
-        const float L = row_sum_fp64(g, V, r, tc, dx, dy, dz);
-        const float p = Store<PT>::ld(proj, j);
+        const float L = row_sum_fp64(g, V, r, dz);
+        const float pj = Store<PT>::ld(proj, j);
         const float w = pw ? ld_any(pw, pwt, j) : 1.0f;
-        rho[(size_t)v * g.cols + u] = (L > 0.0f) ? w * (p - acc) / L : 0.0f;
+        rho[(size_t)v * g.cols + u] = (L > 0.0f) ? w * (pj - acc) / L : 0.0f;
     }
 }
 
-__global__ __launch_bounds__(64) void rowsum_kernel(GeomDev g, float *__restrict__ out, int view_begin) {
+__global__ __launch_bounds__(256) void rowsum_kernel(GeomDev g, float *__restrict__ out, int view_begin) {
+    extern __shared__ float2 smem[];
+    const Tabs T = stage_tables(g, smem);
+    __syncthreads();
     const int k = view_begin + blockIdx.y;
-    const int tiles_u = (g.cols + 7) >> 3;
-    const int u = (blockIdx.x % tiles_u) * 8 + (threadIdx.x & 7);
-    const int v = (blockIdx.x / tiles_u) * 8 + (threadIdx.x >> 3);
+    const int tiles_u = (g.cols + 15) / 16;
+    const int u = (blockIdx.x % tiles_u) * 16 + (threadIdx.x & 15);
+    const int v = (blockIdx.x / tiles_u) * 16 + (threadIdx.x >> 4);
     if (u >= g.cols || v >= g.rows) return;
     const ViewDev &V = g.views[k];
     RayF r;
-    double tc, dx, dy, dz;
-    ray_geom(g, V, u, v, r, tc, dx, dy, dz);
-    out[((size_t)k * g.rows + v) * g.cols + u] = row_sum_fp64(g, V, r, tc, dx, dy, dz);
+    double dz;
+    ray_geom(g, T, V, u, v, r, dz);
+    out[((size_t)k * g.rows + v) * g.cols + u] = row_sum_fp64(g, V, r, dz);
 }
 
 // ------------------------------------------------------------ back-projection
@@ -454,11 +504,11 @@ __device__ __forceinline__ float wave_max(float x) {
 // polygon corner; the polygon circumscribes the outer arc).  Points with
 // pt >= count leave the box untouched.  Sets `behind` if the point is not in
 // front of the source.
-__device__ __forceinline__ void footprint_point(const GeomDev &g, const ViewDev &V, const Block &B, int pt,
-                                                float &umin, float &umax, float &vmin, float &vmax,
+__device__ __forceinline__ void footprint_point(const GeomDev &g, const Tabs &T, const ViewDev &V, const Block &B,
+                                                int pt, float &umin, float &umax, float &vmin, float &vmax,
                                                 float &behind) {
-    const float rO = g.r_tab[B.rB].x * (1.0f + 1e-6f) + 1e-6f;
-    const float rI = g.r_tab[B.rA].x;
+    const float rO = T.r[B.rB].x * (1.0f + 1e-6f) + 1e-6f;
+    const float rI = T.r[B.rA].x;
     const bool full = (B.tB - B.tA) >= g.n_theta;
     const int pi = pt >> 1;
     int npoly;
@@ -486,7 +536,7 @@ __device__ __forceinline__ void footprint_point(const GeomDev &g, const ViewDev 
         }
     }
     if (pi >= npoly) return;
-    const float pz = (pt & 1) ? g.h_tab[B.hB].x + 1e-5f : g.h_tab[B.hA].x - 1e-5f;
+    const float pz = (pt & 1) ? T.h[B.hB].x + 1e-5f : T.h[B.hA].x - 1e-5f;
     const float X = px - V.af[0], Y = py - V.af[1], Z = pz - V.af[2];
     const float lam = V.Qi[0] * X + V.Qi[1] * Y + V.Qi[2] * Z;
     const float uu = V.Qi[3] * X + V.Qi[4] * Y + V.Qi[5] * Z;
@@ -514,8 +564,8 @@ __device__ __forceinline__ bool footprint_box(const GeomDev &g, float umin, floa
         return true;
     }
     const float m = 0.05f;
-    float fu0 = fmaxf(ceilf(umin - m), 0.0f), fu1 = fminf(floorf(umax + m), (float)(g.cols - 1));
-    float fv0 = fmaxf(ceilf(vmin - m), 0.0f), fv1 = fminf(floorf(vmax + m), (float)(g.rows - 1));
+    const float fu0 = fmaxf(ceilf(umin - m), 0.0f), fu1 = fminf(floorf(umax + m), (float)(g.cols - 1));
+    const float fv0 = fmaxf(ceilf(vmin - m), 0.0f), fv1 = fminf(floorf(vmax + m), (float)(g.rows - 1));
     if (!(fu1 >= fu0 && fv1 >= fv0)) return false;
     u0 = (int)fu0;
     u1 = (int)fu1;
@@ -526,10 +576,10 @@ __device__ __forceinline__ bool footprint_box(const GeomDev &g, float umin, floa
 
 // Detector box of the block in view V; the whole wave participates (each lane
 // projects one hull point, then min/max across the wave).
-__device__ bool footprint(const GeomDev &g, const ViewDev &V, const Block &B, int &u0, int &u1, int &v0,
-                          int &v1) {
+__device__ bool footprint(const GeomDev &g, const Tabs &T, const ViewDev &V, const Block &B, int &u0, int &u1,
+                          int &v0, int &v1) {
     float umin = CYL_INF, umax = -CYL_INF, vmin = CYL_INF, vmax = -CYL_INF, behind = 0.0f;
-    footprint_point(g, V, B, threadIdx.x & 63, umin, umax, vmin, vmax, behind);
+    footprint_point(g, T, V, B, threadIdx.x & 63, umin, umax, vmin, vmax, behind);
     umin = wave_min(umin);
     umax = wave_max(umax);
     vmin = wave_min(vmin);
@@ -540,30 +590,30 @@ __device__ bool footprint(const GeomDev &g, const ViewDev &V, const Block &B, in
 
 // Parameter interval of the ray inside the block hull (slab x wedge x disc),
 // from the same crossing formulas as the traversal.
-__device__ __forceinline__ bool clip_block(const GeomDev &g, const ViewDev &V, const RayF &r, const Block &B,
-                                           float &s0, float &s1) {
+__device__ __forceinline__ bool clip_block(const GeomDev &g, const Tabs &T, const ViewDev &V, const RayF &r,
+                                           const Block &B, float &s0, float &s1) {
     s0 = r.s_in;
     s1 = r.s_out;
     if (r.ez != 0.0f) {
-        float t1 = plane_s(g.h_tab[B.hA], r), t2 = plane_s(g.h_tab[B.hB], r);
+        const float t1 = plane_s(T.h[B.hA], r), t2 = plane_s(T.h[B.hB], r);
         s0 = fmaxf(s0, fminf(t1, t2));
         s1 = fminf(s1, fmaxf(t1, t2));
-    } else if (!(r.zc >= g.h_tab[B.hA].x && r.zc < g.h_tab[B.hB].x)) {
+    } else if (!(r.zc >= T.h[B.hA].x && r.zc < T.h[B.hB].x)) {
         return false;
     }
     if (!(r.flags & RAY_AXIAL)) {
-        float w = shell_w(g.r_tab[B.rB], r);
+        const float w = shell_w(T.r[B.rB], r);
         if (w < 0.0f) return false;
         s0 = fmaxf(s0, -w);
         s1 = fminf(s1, w);
     } else {
-        float2 rt = g.r_tab[B.rB];
+        const float2 rt = T.r[B.rB];
         if (!((rt.x - r.b) + (rt.y - r.blo) > 0.0f)) return false;
     }
     if (B.tB - B.tA < g.n_theta) {
         // lower edge: n_A . p >= 0 ; upper edge: n_B . p <= 0
         for (int e = 0; e < 2; ++e) {
-            const EdgeX x = edge_cross(g, V, r, e == 0 ? B.tA : B.tB);
+            const EdgeX x = edge_cross(g, T, V, r, e == 0 ? B.tA : B.tB);
             const float sg = e == 0 ? 1.0f : -1.0f;
             if (x.ne == 0.0f) {
                 if (sg * x.nc < 0.0f) return false;
@@ -579,26 +629,28 @@ __device__ __forceinline__ bool clip_block(const GeomDev &g, const ViewDev &V, c
 }
 
 // Trace ray (u, v) of view V through block B and add t_jm * yj (and t_jm if
-// COLSUM) into the block accumulators.
+// COLSUM) into the block accumulators; cells outside the block (rounding at
+// its faces) go to the spare slot acc[ncell].
 template <bool COLSUM>
-__device__ __forceinline__ void bp_ray(const GeomDev &g, const ViewDev &V, const Block &B, int u, int v,
-                                       float yj, float *acc_c, float *acc_n) {
+__device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const ViewDev &V, const Block &B, int u,
+                                       int v, float yj, float *acc_c, float *acc_n) {
     const int wt = B.tB - B.tA, wr = B.rB - B.rA;
+    const int spare = (B.hB - B.hA) * wt * wr;
     RayF r;
-    double tc, dx, dy, dz;
-    ray_geom(g, V, u, v, r, tc, dx, dy, dz);
+    double dz;
+    ray_geom(g, T, V, u, v, r, dz);
     if (!(r.flags & RAY_HIT)) return;
     float s0, s1;
-    if (!clip_block(g, V, r, B, s0, s1)) return;
-    // the hull includes the block's inner hole r < r_A: split the
-    // interval there so the walk covers the block cells only
+    if (!clip_block(g, T, V, r, B, s0, s1)) return;
+    // the hull includes the block's inner hole r < r_A: split the interval
+    // there so the walk covers the block cells only
     float pa0 = s0, pa1 = s1, pb0 = 1.0f, pb1 = 0.0f;
-    if (g.r_tab[B.rA].x > 0.0f) {
+    if (T.r[B.rA].x > 0.0f) {
         if (r.flags & RAY_AXIAL) {
-            float2 rt = g.r_tab[B.rA];
+            const float2 rt = T.r[B.rA];
             if ((rt.x - r.b) + (rt.y - r.blo) > 0.0f) return;
         } else {
-            const float wA = shell_w(g.r_tab[B.rA], r);
+            const float wA = shell_w(T.r[B.rA], r);
             if (wA >= 0.0f) {
                 pa1 = fminf(s1, -wA);
                 pb0 = fmaxf(s0, wA);
@@ -607,11 +659,10 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const ViewDev &V, const
         }
     }
     auto visit = [&](int h, int t, int q, float len) {
-        if (q >= B.rA && q < B.rB && h >= B.hA && h < B.hB && t >= B.tA && t < B.tB) {
-            const int loc = ((h - B.hA) * wt + (t - B.tA)) * wr + (q - B.rA);
-            atomicAdd(&acc_c[loc], len * yj);
-            if (COLSUM) atomicAdd(&acc_n[loc], len);
-        }
+        const bool in = q >= B.rA && q < B.rB && h >= B.hA && h < B.hB && t >= B.tA && t < B.tB;
+        const int loc = in ? ((h - B.hA) * wt + (t - B.tA)) * wr + (q - B.rA) : spare;
+        atomicAdd(&acc_c[loc], len * yj);
+        if (COLSUM) atomicAdd(&acc_n[loc], len);
     };
     for (int piece = 0; piece < 2; ++piece) {
         const float a0 = piece ? pb0 : pa0, a1 = piece ? pb1 : pa1;
@@ -628,53 +679,64 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const ViewDev &V, const
             if (dhi < 0) dhi += g.n_theta;
             it = dlo <= dhi ? B.tA : B.tB - 1;
         }
-        traverse(g, V, r, a0, a1, ih, it, ir, visit);
+        traverse(g, T, V, r, a0, a1, ih, it, ir, visit);
     }
 }
 
-// One wave owns one block of cells; it loops over the views, over the
-// detector pixels of the block footprint, traces each ray through the block
-// hull and accumulates c_m = sum t_jm y_j and n_m = sum t_jm in wave-private
-// LDS.  MODE 0: vol = (accumulate ? vol : 0) + c.  MODE 1 (SART, one view):
+// Workgroup of 4 waves; each wave owns one block of cells and loops over the
+// views, over the detector pixels of the block footprint, traces each ray
+// through the block hull and accumulates c_m = sum t_jm y_j and
+// n_m = sum t_jm in wave-private LDS (deterministic: no wave shares a slot).
+// MODE 0: vol = (accumulate ? vol : 0) + c.  MODE 1 (SART, one view):
 // vol += lam * wv * c / n where n > 0.
 template <int VT, int PT, int MODE>
-__global__ __launch_bounds__(64) void bp_kernel(GeomDev g, const void *__restrict__ y, int view_begin,
-                                                int view_end, void *__restrict__ vol, int accumulate,
-                                                const float *__restrict__ rho,
-                                                const void *__restrict__ vw, int vwt, float lam,
-                                                int nonneg) {
-    __shared__ float acc_c[kBlockCells];
-    __shared__ float acc_n[kBlockCells];
-    const int lane = threadIdx.x;
-    const Block B = block_of(g, blockIdx.x);
+__global__ __launch_bounds__(256) void bp_kernel(GeomDev g, const void *__restrict__ y, int view_begin, int view_end,
+                                                 void *__restrict__ vol, int accumulate, const float *__restrict__ rho,
+                                                 const void *__restrict__ vw, int vwt, float lam, int nonneg) {
+    extern __shared__ float2 smem[];
+    const Tabs T = stage_tables(g, smem);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slots = g.bh * g.bt * g.br + 1;
+    float *acc_c = (float *)(smem + table_floats2(g)) + wave * slots * (MODE == 1 ? 2 : 1);
+    float *acc_n = acc_c + slots;
+    const int nblk = g.nbh * g.nbt * g.nbr;
+    int bid = blockIdx.x;
+    const int ngroups = gridDim.x;
+    if ((ngroups & 7) == 0) bid = (blockIdx.x & 7) * (ngroups >> 3) + (blockIdx.x >> 3);
+    const int b = bid * 4 + wave;
+    const bool live = b < nblk;
+    const Block B = block_of(g, live ? b : 0);
     const int wt = B.tB - B.tA, wr = B.rB - B.rA;
     const int ncell = (B.hB - B.hA) * wt * wr;
-    for (int i = lane; i < ncell; i += 64) {
+    for (int i = lane; i <= ncell; i += 64) {
         acc_c[i] = 0.0f;
-        acc_n[i] = 0.0f;
+        if (MODE == 1) acc_n[i] = 0.0f;
     }
     __syncthreads();
-    for (int k = view_begin; k < view_end; ++k) {
-        const ViewDev &V = g.views[k];
-        int u0, u1, v0, v1;
-        if (!footprint(g, V, B, u0, u1, v0, v1)) continue;
-        const int nu = u1 - u0 + 1;
-        const int npix = nu * (v1 - v0 + 1);
-        for (int base = 0; base < npix; base += 64) {
-            const int p = base + lane;
-            if (p >= npix) continue;
-            const int v = v0 + p / nu;
-            const int u = u0 + p % nu;
-            float yj;
-            if (MODE == 1)
-                yj = rho[(size_t)v * g.cols + u];
-            else
-                yj = Store<PT>::ld(y, ((size_t)k * g.rows + v) * g.cols + u);
-            if (MODE == 0 && yj == 0.0f) continue;
-            bp_ray<(MODE == 1)>(g, V, B, u, v, yj, acc_c, acc_n);
+    if (live) {
+        for (int k = view_begin; k < view_end; ++k) {
+            const ViewDev &V = g.views[k];
+            int u0, u1, v0, v1;
+            if (!footprint(g, T, V, B, u0, u1, v0, v1)) continue;
+            const int nu = u1 - u0 + 1;
+            const int npix = nu * (v1 - v0 + 1);
+            for (int base = 0; base < npix; base += 64) {
+                const int p = base + lane;
+                if (p >= npix) continue;
+                const int v = v0 + p / nu;
+                const int u = u0 + p % nu;
+                float yj;
+                if (MODE == 1)
+                    yj = rho[(size_t)v * g.cols + u];
+                else
+                    yj = Store<PT>::ld(y, ((size_t)k * g.rows + v) * g.cols + u);
+                if (MODE == 0 && yj == 0.0f) continue;
+                bp_ray<(MODE == 1)>(g, T, V, B, u, v, yj, acc_c, acc_n);
+            }
         }
     }
     __syncthreads();
+    if (!live) return;
     for (int i = lane; i < ncell; i += 64) {
         const int q = i % wr;
         const int t = (i / wr) % wt;
@@ -706,15 +768,35 @@ static int launch_check(const char *what) {
     return CYL_OK;
 }
 
+static size_t table_bytes(const GeomDev &g) {
+    return sizeof(float2) * ((size_t)(g.n_r + 1) + (g.n_h + 1) + (g.n_theta + 1));
+}
+
+static size_t bp_lds_bytes(const GeomDev &g, bool sart) {
+    return table_bytes(g) + 4 * sizeof(float) * (size_t)(g.bh * g.bt * g.br + 1) * (sart ? 2 : 1);
+}
+
+// Rays per launch below which each ray is split over neighbouring lanes so one
+// view still fills the GPU.
+static int fp_split(const GeomDev &g, int nv) {
+    const long rays = (long)g.rows * g.cols * nv;
+    if (rays >= (4L << 20)) return 1;
+    if (rays >= (1L << 20)) return 2;
+    return 4;
+}
+
 template <int VT, int PT>
-static void launch_fp_t(const cyl_geom *G, const void *vol, void *proj, int vb, int nv, bool sart,
-                        const void *pw, int pwt, float *rho, hipStream_t st) {
+static void launch_fp_t(const cyl_geom *G, const void *vol, void *proj, int vb, int nv, bool sart, const void *pw,
+                        int pwt, float *rho, hipStream_t st) {
     const GeomDev &g = G->dev;
-    dim3 grid(((g.cols + 7) / 8) * ((g.rows + 7) / 8), nv);
+    const int ns = fp_split(g, nv);
+    const int th = 256 / ns / 16;
+    dim3 grid(((g.cols + 15) / 16) * ((g.rows + th - 1) / th), nv);
+    const size_t lds = table_bytes(g);
     if (sart)
-        hipLaunchKernelGGL((fp_kernel<VT, PT, true>), grid, dim3(64), 0, st, g, vol, proj, vb, pw, pwt, rho);
+        hipLaunchKernelGGL((fp_kernel<VT, PT, true>), grid, dim3(256), lds, st, g, vol, proj, vb, ns, pw, pwt, rho);
     else
-        hipLaunchKernelGGL((fp_kernel<VT, PT, false>), grid, dim3(64), 0, st, g, vol, proj, vb, pw, pwt, rho);
+        hipLaunchKernelGGL((fp_kernel<VT, PT, false>), grid, dim3(256), lds, st, g, vol, proj, vb, ns, pw, pwt, rho);
 }
 
 template <int VT>
@@ -740,12 +822,14 @@ template <int VT, int PT>
 static void launch_bp_t(const cyl_geom *G, const void *y, int vb, int ve, void *vol, int accumulate, bool sart,
                         const float *rho, const void *vw, int vwt, float lam, int nonneg, hipStream_t st) {
     const GeomDev &g = G->dev;
-    dim3 grid(g.nbh * g.nbt * g.nbr);
+    const int nblk = g.nbh * g.nbt * g.nbr;
+    dim3 grid((nblk + 3) / 4);
+    const size_t lds = bp_lds_bytes(g, sart);
     if (sart)
-        hipLaunchKernelGGL((bp_kernel<VT, PT, 1>), grid, dim3(64), 0, st, g, y, vb, ve, vol, accumulate, rho, vw,
+        hipLaunchKernelGGL((bp_kernel<VT, PT, 1>), grid, dim3(256), lds, st, g, y, vb, ve, vol, accumulate, rho, vw,
                            vwt, lam, nonneg);
     else
-        hipLaunchKernelGGL((bp_kernel<VT, PT, 0>), grid, dim3(64), 0, st, g, y, vb, ve, vol, accumulate, rho, vw,
+        hipLaunchKernelGGL((bp_kernel<VT, PT, 0>), grid, dim3(256), lds, st, g, y, vb, ve, vol, accumulate, rho, vw,
                            vwt, lam, nonneg);
 }
 
@@ -857,8 +941,8 @@ extern "C" int cyl_row_sums(const cyl_geom *G, float *out, int32_t view_begin, i
         return CYL_EDEVICE;
     }
     const GeomDev &g = G->dev;
-    dim3 grid(((g.cols + 7) / 8) * ((g.rows + 7) / 8), view_end - view_begin);
-    hipLaunchKernelGGL(rowsum_kernel, grid, dim3(64), 0, (hipStream_t)hip_stream, g, out, view_begin);
+    dim3 grid(((g.cols + 15) / 16) * ((g.rows + 15) / 16), view_end - view_begin);
+    hipLaunchKernelGGL(rowsum_kernel, grid, dim3(256), table_bytes(g), (hipStream_t)hip_stream, g, out, view_begin);
     return launch_check("cyl_row_sums");
 }
 

@@ -52,7 +52,9 @@ def _edge_scans():
         out.append((name, I.Scan(grid, views, 8, 6, np.eye(3), np.zeros(3))))
         out.append((name + "_posed", I.Scan(grid, views, 8, 6, R, T)))
     # odd detector: the central column's rays pass exactly through the axis
-    g = I.Grid(6, 24, 6, 0.0, 6.0, -3.0, 3.0)
+    # (theta0 keeps them off the sector-edge planes; in-plane rays are a tie
+    # case checked by sums only, below)
+    g = I.Grid(6, 24, 6, 0.0, 6.0, -3.0, 3.0, 0.05)
     out.append(("through_axis", I.Scan(g, I.circular_views(4, 40.0, 80.0, 0.7), 9, 11,
                                        np.eye(3), np.zeros(3))))
     # ragged 8x8 tiles and a tilted object
@@ -101,6 +103,26 @@ def test_fp_bp_tiny_all_views(torch_cuda):
 def test_fp_bp_edge_grids(torch_cuda, case):
     name, scan = case
     _fp_bp_check(torch_cuda, scan, 0, scan.n_views, 4011, name)
+
+
+def test_rays_in_sector_edge_planes_sums(torch_cuda):
+    """Rays lying exactly in a sector-edge plane (and through the axis): the
+    side they are given is a rounding tie, so compare what is unique: the FP
+    of a theta-independent volume, and the BP summed over theta."""
+    g = I.Grid(6, 24, 6, 0.0, 6.0, -3.0, 3.0)
+    scan = I.Scan(g, I.circular_views(4, 40.0, 80.0, 0.7), 9, 11, np.eye(3), np.zeros(3))
+    o = ref.Oracle(scan)
+    G = _geom(scan)
+    hr = I.uniform_vector(g.n_h * g.n_r, 21).reshape(g.n_h, 1, g.n_r)
+    x = np.repeat(hr, g.n_theta, axis=1).astype(np.float32)
+    say("in-plane rays fp")
+    q = host(G.fp(dev(x)))
+    assert rel_l2(q, o.fp(x.astype(np.float64))) <= FP_TOL
+    y = I.uniform_vector(scan.n_views * scan.det_rows * scan.det_cols, 22).astype(np.float32)
+    say("in-plane rays bp")
+    b = host(G.bp(dev(y.reshape(scan.proj_shape))))
+    b_ref = o.bp(y.astype(np.float64))
+    assert rel_l2(b.sum(axis=1), b_ref.sum(axis=1)) <= BP_TOL
 
 
 def test_fp_bp_view_subrange_and_accumulate(torch_cuda):
