@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-views", type=int, default=120,
                     help="views in the per-kernel HIP-event timing pass")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -154,6 +156,15 @@ def main():
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     iter_bytes = scan.n_views * (fp_bytes + bp_bytes)
     path_gbs = iter_bytes * it_s / 1e9
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -211,6 +212,16 @@ extern "C" int cyl_geom_create(const cyl_grid *grid, const cyl_traj *traj, const
         cs64[b] = make_double2(std::cos(th), std::sin(th));
         cs[b] = make_float2((float)cs64[b].x, (float)cs64[b].y);
     }
+    // edge n_theta is edge 0 (theta0 + 2 pi), and for even n_theta edge
+    // b + n_theta/2 lies on the same line as edge b: give each line a single
+    // representation so that neighbouring sectors share their edges exactly
+    if (g.n_theta % 2 == 0)
+        for (int b = 0; b < g.n_theta / 2; ++b) {
+            cs64[b + g.n_theta / 2] = make_double2(-cs64[b].x, -cs64[b].y);
+            cs[b + g.n_theta / 2] = make_float2(-cs[b].x, -cs[b].y);
+        }
+    cs64[g.n_theta] = cs64[0];
+    cs[g.n_theta] = cs[0];
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t off_views = 0;
     size_t off_r = align(off_views + sizeof(ViewDev) * nv);
@@ -281,6 +292,16 @@ extern "C" int cyl_geom_create(const cyl_grid *grid, const cyl_traj *traj, const
     if (bt < 1) bt = 1;
     if (bt > 16) bt = 16;
     d.bt = bt;
+    // tuning override "bh,bt,br" (cells per block), used by block-shape sweeps
+    if (const char *env = getenv("CYL_BP_BLOCK")) {
+        int a = 0, b = 0, c = 0;
+        if (sscanf(env, "%d,%d,%d", &a, &b, &c) == 3 && a >= 1 && b >= 1 && c >= 1 &&
+            a * b * c <= kBlockCells) {
+            d.bh = a < g.n_h ? a : g.n_h;
+            d.bt = b < g.n_theta / 2 ? b : (g.n_theta / 2 > 0 ? g.n_theta / 2 : 1);
+            d.br = c < g.n_r ? c : g.n_r;
+        }
+    }
     // shrink the block until 4 accumulator blocks (c and n) fit beside the tables
     while ((size_t)4 * 2 * 4 * (d.bh * d.bt * d.br + 1) + table_bytes > kMaxLds) {
         if (d.br > 4)

@@ -616,7 +616,9 @@ __device__ __forceinline__ bool clip_block(const GeomDev &g, const Tabs &T, cons
             const EdgeX x = edge_cross(g, T, V, r, e == 0 ? B.tA : B.tB);
             const float sg = e == 0 ? 1.0f : -1.0f;
             if (x.ne == 0.0f) {
-                if (sg * x.nc < 0.0f) return false;
+                // parallel to the edge line: a ray on the line belongs to the
+                // sector on the + side, i.e. to the block whose lower edge it is
+                if (e == 0 ? (x.nc < 0.0f) : (x.nc >= 0.0f)) return false;
                 continue;
             }
             if (sg * x.ne > 0.0f)
