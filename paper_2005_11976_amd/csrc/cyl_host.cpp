@@ -108,8 +108,9 @@ extern "C" int cyl_geom_create(const cyl_grid *grid, const cyl_traj *traj, const
         set_error("cyl_geom_create: trajectory needs n_views, det_rows, det_cols >= 1 and views");
         return CYL_EINVAL;
     }
-    if ((int64_t)traj->det_rows * traj->det_cols > (int64_t)1 << 28) {
-        set_error("cyl_geom_create: detector larger than 2^28 pixels");
+    if ((int64_t)traj->det_rows * traj->det_cols > (int64_t)1 << 28 || traj->det_rows > 32767 ||
+        traj->det_cols > 65535) {
+        set_error("cyl_geom_create: detector larger than 2^28 pixels, 32767 rows or 65535 columns");
         return CYL_EINVAL;
     }
     // pose must be a rotation
@@ -276,6 +277,8 @@ extern "C" int cyl_geom_create(const cyl_grid *grid, const cyl_traj *traj, const
     d.inv_dr = (float)(1.0 / dr);
     d.inv_dh = (float)(1.0 / dh);
     d.inv_dtheta = (float)(1.0 / dth);
+    d.dr_lo = (float)(dr - (double)d.dr);
+    d.dh_lo = (float)(dh - (double)d.dh);
     d.r_min_d = g.r_min;
     d.r_max_d = g.r_max;
     d.h_min_d = g.h_min;
@@ -303,7 +306,7 @@ extern "C" int cyl_geom_create(const cyl_grid *grid, const cyl_traj *traj, const
         }
     }
     // shrink the block until 4 accumulator blocks (c and n) fit beside the tables
-    while ((size_t)4 * 2 * 4 * (d.bh * d.bt * d.br + 1) + table_bytes > kMaxLds) {
+    while ((size_t)4 * 2 * 4 * (d.bh * (d.bt * (d.br + 1) + 1) + 1) + table_bytes > kMaxLds) {
         if (d.br > 4)
             d.br /= 2;
         else if (d.bt > 1)

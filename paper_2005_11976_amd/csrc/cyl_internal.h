@@ -27,6 +27,7 @@ struct GeomDev {
     int32_t n_views, rows, cols;
     float r_min, dr, h_min, dh, theta0, dtheta;
     float inv_dr, inv_dh, inv_dtheta;
+    float dr_lo, dh_lo;  // dr - (float)dr, dh - (float)dh
     double r_min_d, r_max_d, h_min_d, h_max_d;
     const float2 *r_tab;   // n_r + 1 shell radii as (hi, lo) float pairs
     const float2 *h_tab;   // n_h + 1 axial planes as (hi, lo)

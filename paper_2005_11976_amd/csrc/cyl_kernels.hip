@@ -114,8 +114,7 @@ struct RayF {
     int flags;
     int it_in, it_out; // sectors before / after the axis for rays through it
     float len;         // |d|
-    double dxd, dyd;   // xy of the FP64 direction d (source -> pixel centre)
-    double tcd;        // FP64 closest-approach parameter (s = (t - tc) |d|)
+    int pix;           // u | v << 16 (the rare FP64 path rebuilds the ray from it)
 };
 
 // Sector containing the direction (x, y).
@@ -157,30 +156,39 @@ struct EdgeX {
     bool on_edge;
 };
 
-__device__ __forceinline__ EdgeX edge_cross(const GeomDev &g, const Tabs &T, const ViewDev &V, const RayF &r,
-                                            int b) {
+// FP64 re-solve of a sector-edge crossing for a ray nearly parallel to the
+// edge line (rare: rays within a few mm of the axis).
+__device__ __forceinline__ void edge_cross_fp64(double2 c, const ViewDev *V, int pix, float len, EdgeX *x) {
+    const double fu = (double)(pix & 0xffff), fv = (double)(pix >> 16);
+    const double dxd = fma(fv, V->V[0], fma(fu, V->U[0], V->d0[0]));
+    const double dyd = fma(fv, V->V[1], fma(fu, V->U[1], V->d0[1]));
+    const double A = fma(dxd, dxd, dyd * dyd);
+    const double tcd = A > 0.0 ? -fma(V->a[0], dxd, V->a[1] * dyd) / A : 0.0;
+    const double nd = c.x * dyd - c.y * dxd;
+    const double na = c.x * V->a[1] - c.y * V->a[0];
+    x->ne = (float)nd;
+    x->nc = (float)na;
+    if (nd == 0.0) {
+        x->on_edge = false;
+        x->s = CYL_INF;
+        return;
+    }
+    const double t = -na / nd;
+    const double px = fma(t, dxd, V->a[0]), py = fma(t, dyd, V->a[1]);
+    x->on_edge = (c.x * px + c.y * py) > 0.0;
+    x->s = (float)((t - tcd) * (double)len);
+}
+
+// cs: (cos, sin) of edge b (from the table).  refine = false skips the FP64
+// re-solve (for candidates that are computed but not used).
+__device__ __forceinline__ EdgeX edge_cross(const GeomDev &g, const ViewDev &V, const RayF &r, float2 cs, int b,
+                                            bool refine = true) {
     EdgeX x;
-    const float2 cs = T.cs[b];
     x.nc = cs.x * r.cy - cs.y * r.cx;
     x.ne = cs.x * r.ey - cs.y * r.ex;
     x.on_edge = (cs.x * r.cx + cs.y * r.cy) > 0.0f;
     x.s = -x.nc * frcp(x.ne);
-    if (fabsf(x.ne) < kEdgeTau) {
-        const double2 c = g.cs64[b];
-        const double nd = c.x * r.dyd - c.y * r.dxd;
-        const double na = c.x * V.a[1] - c.y * V.a[0];
-        x.ne = (float)nd;
-        x.nc = (float)na;
-        if (nd == 0.0) {
-            x.on_edge = false;
-            x.s = CYL_INF;
-        } else {
-            const double t = -na / nd;
-            const double px = fma(t, r.dxd, V.a[0]), py = fma(t, r.dyd, V.a[1]);
-            x.on_edge = (c.x * px + c.y * py) > 0.0;
-            x.s = (float)((t - r.tcd) * (double)r.len);
-        }
-    }
+    if (refine && fabsf(x.ne) < kEdgeTau && !(r.flags & RAY_AXIAL)) edge_cross_fp64(g.cs64[b], &V, r.pix, r.len, &x);
     return x;
 }
 
@@ -188,11 +196,13 @@ __device__ __forceinline__ EdgeX edge_cross(const GeomDev &g, const Tabs &T, con
 // direction, the closest-approach parameter (one FP64 Newton step on an FP32
 // quotient), the closest point and its distance.
 __device__ __forceinline__ void ray_geom(const GeomDev &g, const Tabs &T, const ViewDev &V, int u, int v,
-                                         RayF &r, double &dzo) {
+                                         RayF &r, double &dxo, double &dyo, double &dzo, double &tco) {
     const double fu = (double)u, fv = (double)v;
     const double dx = fma(fv, V.V[0], fma(fu, V.U[0], V.d0[0]));
     const double dy = fma(fv, V.V[1], fma(fu, V.U[1], V.d0[1]));
     const double dz = fma(fv, V.V[2], fma(fu, V.U[2], V.d0[2]));
+    dxo = dx;
+    dyo = dy;
     dzo = dz;
     const double A = fma(dx, dx, dy * dy);
     const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
@@ -203,8 +213,7 @@ __device__ __forceinline__ void ray_geom(const GeomDev &g, const Tabs &T, const 
     r.ez = fdz * il;
     r.flags = 0;
     r.len = len;
-    r.dxd = dx;
-    r.dyd = dy;
+    r.pix = u | (v << 16);
     r.it_in = r.it_out = 0;
     double tc;
     if (A > 0.0) {
@@ -222,7 +231,7 @@ __device__ __forceinline__ void ray_geom(const GeomDev &g, const Tabs &T, const 
         tc = tc < 0.0 ? 0.0 : (tc > 1.0 ? 1.0 : tc);
         r.inv_k = CYL_INF;
     }
-    r.tcd = tc;
+    tco = tc;
     const double cxd = fma(tc, dx, V.a[0]);
     const double cyd = fma(tc, dy, V.a[1]);
     const double b2 = fma(cxd, cxd, cyd * cyd);
@@ -265,9 +274,9 @@ __device__ __forceinline__ void ray_geom(const GeomDev &g, const Tabs &T, const 
 }
 
 // Closed-form row sum L_j in FP64: length inside the support minus the hole.
-__device__ __forceinline__ float row_sum_fp64(const GeomDev &g, const ViewDev &V, const RayF &r, double dz) {
+__device__ __forceinline__ float row_sum_fp64(const GeomDev &g, const ViewDev &V, const RayF &r, double dx,
+                                              double dy, double dz, double tc) {
     if (!(r.flags & RAY_HIT)) return 0.0f;
-    const double dx = r.dxd, dy = r.dyd, tc = r.tcd;
     const double A = fma(dx, dx, dy * dy);
     const double len = sqrt(A + dz * dz);
     double lo = -tc * len, hi = (1.0 - tc) * len;
@@ -319,51 +328,86 @@ __device__ __forceinline__ void cell_at(const GeomDev &g, const RayF &r, float s
 
 // ------------------------------------------------------------ traversal
 
-// Next crossing of each family after s, for the current cell.
-__device__ __forceinline__ float next_z(const Tabs &T, const RayF &r, int dir_h, int ih, float s) {
-    const float sz = plane_s(T.h[ih + (dir_h > 0 ? 1 : 0)], r);
-    return dir_h != 0 ? fmaxf(sz, s) : CYL_INF;
+__device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
+
+// Next sector-edge crossing after s through edge b (cs = its cos, sin).  An
+// edge-half-line meeting behind s means the start cell was one sector short
+// (rounding at entry): cross it at once.
+__device__ __forceinline__ float t_cand(const GeomDev &g, const ViewDev &V, const RayF &r, int dir_t, float2 cs,
+                                        int b, float s, bool refine = true) {
+    if (r.flags & RAY_THRU) return s < 0.0f ? 0.0f : CYL_INF;
+    const EdgeX x = edge_cross(g, V, r, cs, b, refine);
+    return (dir_t != 0 && x.on_edge) ? fmaxf(x.s, s) : CYL_INF;
 }
 
-// Shell crossing: inward through the lower radius while before the closest
-// approach and the ray reaches it, else outward through the upper radius.
-__device__ __forceinline__ float next_r(const Tabs &T, const RayF &r, int ir, float s, int &r_dir) {
-    const float2 rl = T.r[ir < 0 ? 0 : ir], ru = T.r[ir + 1];
-    const float dl = (rl.x - r.b) + (rl.y - r.blo);
-    const float du = (ru.x - r.b) + (ru.y - r.blo);
+// Shell and plane offsets of a ray, rebased at the shell nearest to b and the
+// plane nearest to z_c:  r_i - b = (i - ic) dr + (r_ic - b) and
+// h_m - z_c = (m - mc) dh + (h_mc - z_c), with dr, dh as two FP32 words, so
+// the crossings need no table read and keep the precision of r - b at
+// grazing incidence and of h - z_c for shallow rays.
+struct Rebase {
+    int ic, mc;
+    float drc, dzc;
+};
+
+__device__ __forceinline__ Rebase rebase(const GeomDev &g, const Tabs &T, const RayF &r) {
+    Rebase q;
+    q.ic = clampi((int)floorf((r.b - g.r_min) * g.inv_dr + 0.5f), 0, g.n_r);
+    const float2 rt = T.r[q.ic];
+    q.drc = (rt.x - r.b) + (rt.y - r.blo);
+    q.mc = clampi((int)floorf((r.zc - g.h_min) * g.inv_dh + 0.5f), 0, g.n_h);
+    const float2 ht = T.h[q.mc];
+    q.dzc = (ht.x - r.zc) + (ht.y - r.zclo);
+    return q;
+}
+
+// r_i - b
+__device__ __forceinline__ float shell_off(const GeomDev &g, const Rebase &q, int i) {
+    const float k = (float)(i - q.ic);
+    return fmaf(k, g.dr, fmaf(k, g.dr_lo, q.drc));
+}
+
+// Crossing parameter of axial plane m.
+__device__ __forceinline__ float plane_at(const GeomDev &g, const Rebase &q, const RayF &r, int m) {
+    const float k = (float)(m - q.mc);
+    return fmaf(k, g.dh, fmaf(k, g.dh_lo, q.dzc)) * r.inv_ez;
+}
+
+// Next shell crossing after s for ring ir: inward through r_ir while before
+// the closest approach and the ray reaches it, else outward through r_{ir+1}.
+__device__ __forceinline__ float r_cand(const GeomDev &g, const Rebase &q, const RayF &r, int ir, float s,
+                                        int &r_dir) {
+    const float dl = shell_off(g, q, ir);
+    const float du = shell_off(g, q, ir + 1);
     const bool inward = (s < 0.0f) && (ir >= 0) && (dl > 0.0f);
-    const float d = inward ? dl : du;
-    const float w = fsqrt(fmaxf(d, 0.0f) * ((inward ? rl.x : ru.x) + r.b)) * r.inv_k;
+    const float d = fmaxf(inward ? dl : du, 0.0f);
+    const float w = fsqrt(d * (d + 2.0f * r.b)) * r.inv_k;
     r_dir = inward ? -1 : 1;
     return (r.flags & RAY_AXIAL) ? CYL_INF : fmaxf(inward ? -w : w, s);
 }
 
-__device__ __forceinline__ float next_t(const GeomDev &g, const Tabs &T, const ViewDev &V, const RayF &r, int dir_t,
-                                        int it, float s) {
-    if (r.flags & RAY_THRU) return s < 0.0f ? 0.0f : CYL_INF;
-    // an edge-half-line meeting behind s means the start cell was one sector
-    // short (rounding at entry): cross it at once
-    const EdgeX x = edge_cross(g, T, V, r, it + (dir_t > 0 ? 1 : 0));
-    return (dir_t != 0 && x.on_edge) ? fmaxf(x.s, s) : CYL_INF;
-}
-
 // Walk the ray from s to s_end starting in cell (ih, it, ir) and call
 // visit(ih, it, ir, length) for every piece (length 0 allowed; ir = -1 is the
-// hole).  Every step computes all three next-crossing candidates with selects
-// (no divergent branches but the rare FP64 edge case); the visitor is called
-// before the index updates so a gather it issues overlaps them.
+// hole).  Each step computes the three next-crossing candidates with selects
+// (no divergent branch but the rare FP64 edge case); shell and plane
+// crossings are arithmetic, so the only table read per step is the next
+// sector edge.  The visitor runs before the index updates so a gather it
+// issues overlaps them.
 template <class Visit>
 __device__ __forceinline__ void traverse(const GeomDev &g, const Tabs &T, const ViewDev &V, const RayF &r, float s,
                                          const float s_end, int ih, int it, int ir, Visit &visit) {
+    const int nh = g.n_h, nr = g.n_r, nt = g.n_theta;
     const int dir_h = r.ez > 0.0f ? 1 : (r.ez < 0.0f ? -1 : 0);
     const float cross = r.cx * r.ey - r.cy * r.ex;
-    const int dir_t = (g.n_theta == 1 || (r.flags & (RAY_AXIAL | RAY_THRU))) ? 0
-                      : (cross > 0.0f ? 1 : (cross < 0.0f ? -1 : 0));
+    const int dir_t = (nt == 1 || (r.flags & (RAY_AXIAL | RAY_THRU))) ? 0 : (cross > 0.0f ? 1 : (cross < 0.0f ? -1 : 0));
+    const int up_t = dir_t > 0 ? 1 : 0;
+    const int up_h = dir_h > 0 ? 1 : 0;
+    const Rebase q = rebase(g, T, r);
     int r_dir;
-    float s_z = next_z(T, r, dir_h, ih, s);
-    float s_r = next_r(T, r, ir, s, r_dir);
-    float s_t = (g.n_theta == 1) ? CYL_INF : next_t(g, T, V, r, dir_t, it, s);
-    const int max_steps = 2 * g.n_r + g.n_theta + g.n_h + 8;
+    float s_z = dir_h != 0 ? fmaxf(plane_at(g, q, r, ih + up_h), s) : CYL_INF;
+    float s_r = r_cand(g, q, r, ir, s, r_dir);
+    float s_t = (nt == 1) ? CYL_INF : t_cand(g, V, r, dir_t, T.cs[it + up_t], it + up_t, s);
+    const int max_steps = 2 * nr + nt + nh + 8;
     for (int n = 0; n < max_steps; ++n) {
         const float sn = fminf(fminf(s_z, s_r), fminf(s_t, s_end));
         visit(ih, it, ir, sn - s);
@@ -374,17 +418,18 @@ __device__ __forceinline__ void traverse(const GeomDev &g, const Tabs &T, const 
         ih += ev_z ? dir_h : 0;
         ir += ev_r ? r_dir : 0;
         int itn = it + (ev_t ? dir_t : 0);
-        itn = itn < 0 ? itn + g.n_theta : (itn >= g.n_theta ? itn - g.n_theta : itn);
+        itn = itn < 0 ? itn + nt : (itn >= nt ? itn - nt : itn);
         it = (ev_t && (r.flags & RAY_THRU)) ? r.it_out : itn;
-        if (!(sn < s_end) || (unsigned)ih >= (unsigned)g.n_h || ir >= g.n_r) break;
+        if (!(sn < s_end) || (unsigned)ih >= (unsigned)nh || ir >= nr) break;
         int rd;
-        const float nz = next_z(T, r, dir_h, ih, s);
-        const float nr = next_r(T, r, ir, s, rd);
-        const float nt = next_t(g, T, V, r, dir_t, it, s);
+        const float nz = dir_h != 0 ? fmaxf(plane_at(g, q, r, ih + up_h), s) : CYL_INF;
+        const float nrr = r_cand(g, q, r, ir, s, rd);
+        const int be = it + up_t;
+        const float ntt = t_cand(g, V, r, dir_t, T.cs[be], be, s, ev_t);
         s_z = ev_z ? nz : s_z;
-        s_r = ev_r ? nr : s_r;
+        s_r = ev_r ? nrr : s_r;
         r_dir = ev_r ? rd : r_dir;
-        s_t = ev_t ? nt : s_t;
+        s_t = ev_t ? ntt : s_t;
     }
 }
 
@@ -405,48 +450,66 @@ __device__ __forceinline__ float fp_piece(const GeomDev &g, const Tabs &T, const
     int ih, it, ir;
     cell_at(g, r, a0, ih, it, ir);
     const int nt = g.n_theta, nr = g.n_r;
+    // the gather of one step is consumed in the next, so its latency overlaps a
+    // whole traversal step
+    float plen = 0.0f, pval = 0.0f;
     auto visit = [&](int h, int t, int q, float len) {
         const int idx = (h * nt + t) * nr + (q < 0 ? 0 : q);
         const float val = Store<VT>::ld(vol, (size_t)idx);
-        acc = fmaf(q < 0 ? 0.0f : len, val, acc);
+        acc = fmaf(plen, pval, acc);
+        plen = q < 0 ? 0.0f : len;
+        pval = val;
     };
     traverse(g, T, V, r, a0, a1, ih, it, ir, visit);
-    return acc;
+    return fmaf(plen, pval, acc);
 }
 
-// Workgroup of 256 lanes = a 16-wide pixel tile x NSPLIT pieces per ray;
-// blockIdx.y = view offset.  Tiles are spread so that each XCD (blocks are
-// dealt round-robin to the 8 XCDs) works on a contiguous band of rows.
+// Workgroup of 256 lanes (4 waves).  With nsplit pieces per ray the
+// workgroup covers 256 / nsplit rays; wave w takes piece w % nsplit of the
+// 64 rays of pixel group w / nsplit (an 8 x 8 tile), so the lanes of a wave
+// walk the same stretch of neighbouring rays and their gathers stay coherent.
+// Partial sums meet in LDS.  blockIdx.y = view offset.  Tiles are dealt so
+// that each XCD (blocks go round-robin to the 8 XCDs) gets a contiguous band
+// of rows.
 template <int VT, int PT, bool SART>
 __global__ __launch_bounds__(256) void fp_kernel(GeomDev g, const void *__restrict__ vol, void *__restrict__ proj,
                                                  int view_begin, int nsplit, const void *__restrict__ pw, int pwt,
                                                  float *__restrict__ rho) {
     extern __shared__ float2 smem[];
     const Tabs T = stage_tables(g, smem);
+    float *part = (float *)(smem + table_floats2(g));
     __syncthreads();
     const int k = view_begin + blockIdx.y;
-    const int tw = 16, th = 256 / nsplit / 16;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int groups = 4 / nsplit;           // 8x8 pixel groups per workgroup
+    const int piece = wave % nsplit, grp = wave / nsplit;
+    // workgroup tile: 8 * groups wide, 8 high
+    const int tw = 8 * groups;
     const int tiles_u = (g.cols + tw - 1) / tw;
-    const int ntiles = tiles_u * ((g.rows + th - 1) / th);
+    const int ntiles = tiles_u * ((g.rows + 7) / 8);
     int tile = blockIdx.x;
     if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
-    const int p = threadIdx.x / nsplit, piece = threadIdx.x % nsplit;
-    const int u = (tile % tiles_u) * tw + (p % tw);
-    const int v = (tile / tiles_u) * th + (p / tw);
+    const int u = (tile % tiles_u) * tw + grp * 8 + (lane & 7);
+    const int v = (tile / tiles_u) * 8 + (lane >> 3);
     const bool live = u < g.cols && v < g.rows;
     const ViewDev &V = g.views[k];
     RayF r;
-    double dz;
-    ray_geom(g, T, V, live ? u : 0, live ? v : 0, r, dz);
+    double dx, dy, dz, tc;
+    ray_geom(g, T, V, live ? u : 0, live ? v : 0, r, dx, dy, dz, tc);
     if (!live) r.flags = 0;
     float acc = fp_piece<VT>(g, T, V, r, vol, piece, nsplit);
-    for (int o = 1; o < nsplit; o <<= 1) acc += __shfl_xor(acc, o);
-    if (!live || piece != 0) return;
+    if (nsplit > 1) {
+        part[threadIdx.x] = acc;
+        __syncthreads();
+        if (piece != 0) return;
+        for (int p = 1; p < nsplit; ++p) acc += part[threadIdx.x + 64 * p];
+    }
+    if (!live) return;
     const size_t j = ((size_t)k * g.rows + v) * g.cols + u;
     if (!SART) {
         Store<PT>::st(proj, j, acc);
     } else {
-        const float L = row_sum_fp64(g, V, r, dz);
+        const float L = row_sum_fp64(g, V, r, dx, dy, dz, tc);
         const float pj = Store<PT>::ld(proj, j);
         const float w = pw ? ld_any(pw, pwt, j) : 1.0f;
         rho[(size_t)v * g.cols + u] = (L > 0.0f) ? w * (pj - acc) / L : 0.0f;
@@ -464,9 +527,9 @@ __global__ __launch_bounds__(256) void rowsum_kernel(GeomDev g, float *__restric
     if (u >= g.cols || v >= g.rows) return;
     const ViewDev &V = g.views[k];
     RayF r;
-    double dz;
-    ray_geom(g, T, V, u, v, r, dz);
-    out[((size_t)k * g.rows + v) * g.cols + u] = row_sum_fp64(g, V, r, dz);
+    double dx, dy, dz, tc;
+    ray_geom(g, T, V, u, v, r, dx, dy, dz, tc);
+    out[((size_t)k * g.rows + v) * g.cols + u] = row_sum_fp64(g, V, r, dx, dy, dz, tc);
 }
 
 // ------------------------------------------------------------ back-projection
@@ -613,7 +676,8 @@ __device__ __forceinline__ bool clip_block(const GeomDev &g, const Tabs &T, cons
     if (B.tB - B.tA < g.n_theta) {
         // lower edge: n_A . p >= 0 ; upper edge: n_B . p <= 0
         for (int e = 0; e < 2; ++e) {
-            const EdgeX x = edge_cross(g, T, V, r, e == 0 ? B.tA : B.tB);
+            const int eb = e == 0 ? B.tA : B.tB;
+            const EdgeX x = edge_cross(g, V, r, T.cs[eb], eb);
             const float sg = e == 0 ? 1.0f : -1.0f;
             if (x.ne == 0.0f) {
                 // parallel to the edge line: a ray on the line belongs to the
@@ -633,14 +697,24 @@ __device__ __forceinline__ bool clip_block(const GeomDev &g, const Tabs &T, cons
 // Trace ray (u, v) of view V through block B and add t_jm * yj (and t_jm if
 // COLSUM) into the block accumulators; cells outside the block (rounding at
 // its faces) go to the spare slot acc[ncell].
+// Accumulator slot of block-local cell (h, t, q): rows of br + 1 and planes of
+// bt (br + 1) + 1 words, odd strides so neighbouring cells in theta and h fall
+// in different LDS banks.
+__device__ __forceinline__ int slot(const Block &B, int h, int t, int q) {
+    const int rs = (B.rB - B.rA) + 1;
+    const int ps = (B.tB - B.tA) * rs + 1;
+    return h * ps + t * rs + q;
+}
+
+__device__ __forceinline__ int block_slots(const Block &B) { return slot(B, B.hB - B.hA, 0, 0) + 1; }
+
 template <bool COLSUM>
 __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const ViewDev &V, const Block &B, int u,
                                        int v, float yj, float *acc_c, float *acc_n) {
-    const int wt = B.tB - B.tA, wr = B.rB - B.rA;
-    const int spare = (B.hB - B.hA) * wt * wr;
+    const int spare = block_slots(B) - 1;
     RayF r;
-    double dz;
-    ray_geom(g, T, V, u, v, r, dz);
+    double dx, dy, dz, tc;
+    ray_geom(g, T, V, u, v, r, dx, dy, dz, tc);
     if (!(r.flags & RAY_HIT)) return;
     float s0, s1;
     if (!clip_block(g, T, V, r, B, s0, s1)) return;
@@ -662,7 +736,7 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Vi
     }
     auto visit = [&](int h, int t, int q, float len) {
         const bool in = q >= B.rA && q < B.rB && h >= B.hA && h < B.hB && t >= B.tA && t < B.tB;
-        const int loc = in ? ((h - B.hA) * wt + (t - B.tA)) * wr + (q - B.rA) : spare;
+        const int loc = in ? slot(B, h - B.hA, t - B.tA, q - B.rA) : spare;
         atomicAdd(&acc_c[loc], len * yj);
         if (COLSUM) atomicAdd(&acc_n[loc], len);
     };
@@ -697,8 +771,8 @@ __global__ __launch_bounds__(256) void bp_kernel(GeomDev g, const void *__restri
                                                  const void *__restrict__ vw, int vwt, float lam, int nonneg) {
     extern __shared__ float2 smem[];
     const Tabs T = stage_tables(g, smem);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slots = g.bh * g.bt * g.br + 1;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int slots = g.bh * (g.bt * (g.br + 1) + 1) + 1;
     float *acc_c = (float *)(smem + table_floats2(g)) + wave * slots * (MODE == 1 ? 2 : 1);
     float *acc_n = acc_c + slots;
     const int nblk = g.nbh * g.nbt * g.nbr;
@@ -710,7 +784,8 @@ __global__ __launch_bounds__(256) void bp_kernel(GeomDev g, const void *__restri
     const Block B = block_of(g, live ? b : 0);
     const int wt = B.tB - B.tA, wr = B.rB - B.rA;
     const int ncell = (B.hB - B.hA) * wt * wr;
-    for (int i = lane; i <= ncell; i += 64) {
+    const int nslot = block_slots(B);
+    for (int i = lane; i < nslot; i += 64) {
         acc_c[i] = 0.0f;
         if (MODE == 1) acc_n[i] = 0.0f;
     }
@@ -720,6 +795,10 @@ __global__ __launch_bounds__(256) void bp_kernel(GeomDev g, const void *__restri
             const ViewDev &V = g.views[k];
             int u0, u1, v0, v1;
             if (!footprint(g, T, V, B, u0, u1, v0, v1)) continue;
+            u0 = __builtin_amdgcn_readfirstlane(u0);
+            u1 = __builtin_amdgcn_readfirstlane(u1);
+            v0 = __builtin_amdgcn_readfirstlane(v0);
+            v1 = __builtin_amdgcn_readfirstlane(v1);
             const int nu = u1 - u0 + 1;
             const int npix = nu * (v1 - v0 + 1);
             for (int base = 0; base < npix; base += 64) {
@@ -744,14 +823,15 @@ __global__ __launch_bounds__(256) void bp_kernel(GeomDev g, const void *__restri
         const int t = (i / wr) % wt;
         const int h = i / (wr * wt);
         const size_t gi = ((size_t)(B.hA + h) * g.n_theta + (B.tA + t)) * g.n_r + (B.rA + q);
+        const int sl = slot(B, h, t, q);
         if (MODE == 0) {
             const float base = accumulate ? Store<VT>::ld(vol, gi) : 0.0f;
-            Store<VT>::st(vol, gi, base + acc_c[i]);
+            Store<VT>::st(vol, gi, base + acc_c[sl]);
         } else {
-            const float n = acc_n[i];
+            const float n = acc_n[sl];
             if (n > 0.0f) {
                 const float w = vw ? ld_any(vw, vwt, gi) : 1.0f;
-                float m = Store<VT>::ld(vol, gi) + lam * w * acc_c[i] / n;
+                float m = Store<VT>::ld(vol, gi) + lam * w * acc_c[sl] / n;
                 if (nonneg && m < 0.0f) m = 0.0f;
                 Store<VT>::st(vol, gi, m);
             }
@@ -775,7 +855,7 @@ static size_t table_bytes(const GeomDev &g) {
 }
 
 static size_t bp_lds_bytes(const GeomDev &g, bool sart) {
-    return table_bytes(g) + 4 * sizeof(float) * (size_t)(g.bh * g.bt * g.br + 1) * (sart ? 2 : 1);
+    return table_bytes(g) + 4 * sizeof(float) * (size_t)(g.bh * (g.bt * (g.br + 1) + 1) + 1) * (sart ? 2 : 1);
 }
 
 // Rays per launch below which each ray is split over neighbouring lanes so one
@@ -792,9 +872,9 @@ static void launch_fp_t(const cyl_geom *G, const void *vol, void *proj, int vb, 
                         int pwt, float *rho, hipStream_t st) {
     const GeomDev &g = G->dev;
     const int ns = fp_split(g, nv);
-    const int th = 256 / ns / 16;
-    dim3 grid(((g.cols + 15) / 16) * ((g.rows + th - 1) / th), nv);
-    const size_t lds = table_bytes(g);
+    const int tw = 8 * (4 / ns);
+    dim3 grid(((g.cols + tw - 1) / tw) * ((g.rows + 7) / 8), nv);
+    const size_t lds = table_bytes(g) + 256 * sizeof(float);
     if (sart)
         hipLaunchKernelGGL((fp_kernel<VT, PT, true>), grid, dim3(256), lds, st, g, vol, proj, vb, ns, pw, pwt, rho);
     else
