@@ -388,7 +388,8 @@ __device__ __forceinline__ float r_cand(const GeomDev &g, const Rebase &q, const
 
 // Walk the ray from s to s_end starting in cell (ih, it, ir) and call
 // visit(ih, it, ir, length) for every piece (length 0 allowed; ir = -1 is the
-// hole).  Each step computes the three next-crossing candidates with selects
+// hole), and visit.late() at the end of each step (and once after the walk)
+// for work the visitor wants to spread out.  Each step computes the three next-crossing candidates with selects
 // (no divergent branch but the rare FP64 edge case); shell and plane
 // crossings are arithmetic, so the only table read per step is the next
 // sector edge.  The visitor runs before the index updates so a gather it
@@ -410,27 +411,35 @@ __device__ __forceinline__ void traverse(const GeomDev &g, const Tabs &T, const 
     const int max_steps = 2 * nr + nt + nh + 8;
     for (int n = 0; n < max_steps; ++n) {
         const float sn = fminf(fminf(s_z, s_r), fminf(s_t, s_end));
-        visit(ih, it, ir, sn - s);
-        s = sn;
         const bool ev_z = (sn == s_z);
         const bool ev_r = !ev_z && (sn == s_r);
         const bool ev_t = !ev_z && !ev_r;
-        ih += ev_z ? dir_h : 0;
-        ir += ev_r ? r_dir : 0;
+        const int nih = ih + (ev_z ? dir_h : 0);
+        const int nir = ir + (ev_r ? r_dir : 0);
         int itn = it + (ev_t ? dir_t : 0);
         itn = itn < 0 ? itn + nt : (itn >= nt ? itn - nt : itn);
-        it = (ev_t && (r.flags & RAY_THRU)) ? r.it_out : itn;
+        const int nit = (ev_t && (r.flags & RAY_THRU)) ? r.it_out : itn;
+        // read the next sector edge before the visitor's LDS atomics, so that
+        // waiting for it does not wait for them (LDS operations retire in order)
+        const int be = nit + up_t;
+        const float2 cse = T.cs[be];
+        visit(ih, it, ir, sn - s);
+        s = sn;
+        ih = nih;
+        ir = nir;
+        it = nit;
         if (!(sn < s_end) || (unsigned)ih >= (unsigned)nh || ir >= nr) break;
         int rd;
         const float nz = dir_h != 0 ? fmaxf(plane_at(g, q, r, ih + up_h), s) : CYL_INF;
         const float nrr = r_cand(g, q, r, ir, s, rd);
-        const int be = it + up_t;
-        const float ntt = t_cand(g, V, r, dir_t, T.cs[be], be, s, ev_t);
+        const float ntt = t_cand(g, V, r, dir_t, cse, be, s, ev_t);
         s_z = ev_z ? nz : s_z;
         s_r = ev_r ? nrr : s_r;
         r_dir = ev_r ? rd : r_dir;
         s_t = ev_t ? ntt : s_t;
+        visit.late();
     }
+    visit.late();
 }
 
 // ------------------------------------------------------------ forward projection
@@ -441,27 +450,31 @@ __device__ __forceinline__ void traverse(const GeomDev &g, const Tabs &T, const 
 template <int VT>
 __device__ __forceinline__ float fp_piece(const GeomDev &g, const Tabs &T, const ViewDev &V, const RayF &r,
                                           const void *__restrict__ vol, int piece, int npieces) {
-    float acc = 0.0f;
-    if (!(r.flags & RAY_HIT)) return acc;
+    if (!(r.flags & RAY_HIT)) return 0.0f;
     const float span = (r.s_out - r.s_in) / (float)npieces;
     const float a0 = piece == 0 ? r.s_in : fmaf((float)piece, span, r.s_in);
     const float a1 = piece == npieces - 1 ? r.s_out : fmaf((float)(piece + 1), span, r.s_in);
-    if (!(a1 > a0)) return acc;
+    if (!(a1 > a0)) return 0.0f;
     int ih, it, ir;
     cell_at(g, r, a0, ih, it, ir);
     const int nt = g.n_theta, nr = g.n_r;
     // the gather of one step is consumed in the next, so its latency overlaps a
     // whole traversal step
-    float plen = 0.0f, pval = 0.0f;
-    auto visit = [&](int h, int t, int q, float len) {
-        const int idx = (h * nt + t) * nr + (q < 0 ? 0 : q);
-        const float val = Store<VT>::ld(vol, (size_t)idx);
-        acc = fmaf(plen, pval, acc);
-        plen = q < 0 ? 0.0f : len;
-        pval = val;
-    };
+    struct Gather {
+        const void *vol;
+        int nt, nr;
+        float acc, plen, pval;
+        __device__ __forceinline__ void operator()(int h, int t, int q, float len) {
+            const int idx = (h * nt + t) * nr + (q < 0 ? 0 : q);
+            const float val = Store<VT>::ld(vol, (size_t)idx);
+            acc = fmaf(plen, pval, acc);
+            plen = q < 0 ? 0.0f : len;
+            pval = val;
+        }
+        __device__ __forceinline__ void late() {}
+    } visit{vol, nt, nr, 0.0f, 0.0f, 0.0f};
     traverse(g, T, V, r, a0, a1, ih, it, ir, visit);
-    return fmaf(plen, pval, acc);
+    return fmaf(visit.plen, visit.pval, visit.acc);
 }
 
 // Workgroup of 256 lanes (4 waves).  With nsplit pieces per ray the
@@ -710,7 +723,7 @@ __device__ __forceinline__ int block_slots(const Block &B) { return slot(B, B.hB
 
 template <bool COLSUM>
 __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const ViewDev &V, const Block &B, int u,
-                                       int v, float yj, float *acc_c, float *acc_n) {
+                                       int v, float yj, float *acc_c, int *acc_n, float nscale) {
     const int spare = block_slots(B) - 1;
     RayF r;
     double dx, dy, dz, tc;
@@ -734,12 +747,29 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Vi
             }
         }
     }
-    auto visit = [&](int h, int t, int q, float len) {
-        const bool in = q >= B.rA && q < B.rB && h >= B.hA && h < B.hB && t >= B.tA && t < B.tB;
-        const int loc = in ? slot(B, h - B.hA, t - B.tA, q - B.rA) : spare;
-        atomicAdd(&acc_c[loc], len * yj);
-        if (COLSUM) atomicAdd(&acc_n[loc], len);
-    };
+    // c accumulates with a float LDS atomic.  The column sum n, which depends on
+    // the geometry only, accumulates in fixed point with an integer LDS atomic
+    // (far cheaper than a second float atomic on gfx950), issued at the end of
+    // the step; nscale bounds the sum below 2^31 (see bp_kernel).
+    struct Scatter {
+        const Block &B;
+        float *acc_c;
+        int *acc_n;
+        float yj, nscale;
+        int spare, nloc;
+        float nlen;
+        __device__ __forceinline__ void operator()(int h, int t, int q, float len) {
+            const bool in = q >= B.rA && q < B.rB && h >= B.hA && h < B.hB && t >= B.tA && t < B.tB;
+            const int loc = in ? slot(B, h - B.hA, t - B.tA, q - B.rA) : spare;
+            atomicAdd(&acc_c[loc], len * yj);
+            nloc = loc;
+            nlen = len;
+        }
+        __device__ __forceinline__ void late() {
+            if (COLSUM && nlen != 0.0f) atomicAdd(&acc_n[nloc], __float2int_rn(nlen * nscale));
+            nlen = 0.0f;
+        }
+    } visit{B, acc_c, acc_n, yj, nscale, spare, spare, 0.0f};
     for (int piece = 0; piece < 2; ++piece) {
         const float a0 = piece ? pb0 : pa0, a1 = piece ? pb1 : pa1;
         if (!(a1 > a0)) continue;
@@ -774,7 +804,7 @@ __global__ __launch_bounds__(256) void bp_kernel(GeomDev g, const void *__restri
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int slots = g.bh * (g.bt * (g.br + 1) + 1) + 1;
     float *acc_c = (float *)(smem + table_floats2(g)) + wave * slots * (MODE == 1 ? 2 : 1);
-    float *acc_n = acc_c + slots;
+    int *acc_n = (int *)(acc_c + slots);
     const int nblk = g.nbh * g.nbt * g.nbr;
     int bid = blockIdx.x;
     const int ngroups = gridDim.x;
@@ -787,8 +817,14 @@ __global__ __launch_bounds__(256) void bp_kernel(GeomDev g, const void *__restri
     const int nslot = block_slots(B);
     for (int i = lane; i < nslot; i += 64) {
         acc_c[i] = 0.0f;
-        if (MODE == 1) acc_n[i] = 0.0f;
+        if (MODE == 1) acc_n[i] = 0;
     }
+    // fixed-point scale of the column sums (SART launches one view): any chord
+    // through a cell is at most the cell diameter D, and at most npix rays of
+    // the footprint box reach a cell, so n <= D npix; scale that bound to 2^30
+    const float ctheta = (B.tB - B.tA) * g.dtheta >= 3.14159265f ? 2.0f : 2.0f * sinf(0.5f * (B.tB - B.tA) * g.dtheta);
+    const float dcell = sqrtf(g.dh * g.dh + (g.dr + T.r[B.rB].x * ctheta) * (g.dr + T.r[B.rB].x * ctheta)) * 1.001f;
+    float nscale = 1.0f, inv_nscale = 1.0f;
     __syncthreads();
     if (live) {
         for (int k = view_begin; k < view_end; ++k) {
@@ -801,6 +837,12 @@ __global__ __launch_bounds__(256) void bp_kernel(GeomDev g, const void *__restri
             v1 = __builtin_amdgcn_readfirstlane(v1);
             const int nu = u1 - u0 + 1;
             const int npix = nu * (v1 - v0 + 1);
+            if (MODE == 1) {
+                int e;
+                frexpf(1073741824.0f / (dcell * (float)npix), &e);
+                nscale = ldexpf(1.0f, e - 1);
+                inv_nscale = ldexpf(1.0f, 1 - e);
+            }
             for (int base = 0; base < npix; base += 64) {
                 const int p = base + lane;
                 if (p >= npix) continue;
@@ -812,7 +854,7 @@ __global__ __launch_bounds__(256) void bp_kernel(GeomDev g, const void *__restri
                 else
                     yj = Store<PT>::ld(y, ((size_t)k * g.rows + v) * g.cols + u);
                 if (MODE == 0 && yj == 0.0f) continue;
-                bp_ray<(MODE == 1)>(g, T, V, B, u, v, yj, acc_c, acc_n);
+                bp_ray<(MODE == 1)>(g, T, V, B, u, v, yj, acc_c, acc_n, nscale);
             }
         }
     }
@@ -828,7 +870,7 @@ __global__ __launch_bounds__(256) void bp_kernel(GeomDev g, const void *__restri
             const float base = accumulate ? Store<VT>::ld(vol, gi) : 0.0f;
             Store<VT>::st(vol, gi, base + acc_c[sl]);
         } else {
-            const float n = acc_n[sl];
+            const float n = (float)acc_n[sl] * inv_nscale;
             if (n > 0.0f) {
                 const float w = vw ? ld_any(vw, vwt, gi) : 1.0f;
                 float m = Store<VT>::ld(vol, gi) + lam * w * acc_c[sl] / n;
