@@ -82,19 +82,21 @@ struct Tabs {
     const float2 *cs;  // n_theta + 1 sector edges (cos, sin)
 };
 
-__device__ __forceinline__ size_t table_floats2(const GeomDev &g) {
-    return (size_t)(g.n_r + 1) + (g.n_h + 1) + (g.n_theta + 1);
+__device__ __forceinline__ size_t table_floats2(const GeomDev &g, bool all = true) {
+    return (all ? (size_t)(g.n_r + 1) + (g.n_h + 1) : 0) + (g.n_theta + 1);
 }
 
 // Cooperative copy of the grid tables into LDS; the caller synchronises.
-__device__ __forceinline__ Tabs stage_tables(const GeomDev &g, float2 *smem) {
-    const int nr = g.n_r + 1, nh = g.n_h + 1, nc = g.n_theta + 1;
+// all = false stages only the sector edges (the one table the traversal loop
+// reads) and leaves the radii and planes in global memory.
+__device__ __forceinline__ Tabs stage_tables(const GeomDev &g, float2 *smem, bool all = true) {
+    const int nr = all ? g.n_r + 1 : 0, nh = all ? g.n_h + 1 : 0, nc = g.n_theta + 1;
     for (int i = threadIdx.x; i < nr; i += blockDim.x) smem[i] = g.r_tab[i];
     for (int i = threadIdx.x; i < nh; i += blockDim.x) smem[nr + i] = g.h_tab[i];
     for (int i = threadIdx.x; i < nc; i += blockDim.x) smem[nr + nh + i] = g.cs_tab[i];
     Tabs T;
-    T.r = smem;
-    T.h = smem + nr;
+    T.r = all ? smem : g.r_tab;
+    T.h = all ? smem + nr : g.h_tab;
     T.cs = smem + nr + nh;
     return T;
 }
@@ -800,10 +802,10 @@ __global__ __launch_bounds__(256) void bp_kernel(GeomDev g, const void *__restri
                                                  void *__restrict__ vol, int accumulate, const float *__restrict__ rho,
                                                  const void *__restrict__ vw, int vwt, float lam, int nonneg) {
     extern __shared__ float2 smem[];
-    const Tabs T = stage_tables(g, smem);
+    const Tabs T = stage_tables(g, smem, false);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int slots = g.bh * (g.bt * (g.br + 1) + 1) + 1;
-    float *acc_c = (float *)(smem + table_floats2(g)) + wave * slots * (MODE == 1 ? 2 : 1);
+    float *acc_c = (float *)(smem + table_floats2(g, false)) + wave * slots * (MODE == 1 ? 2 : 1);
     int *acc_n = (int *)(acc_c + slots);
     const int nblk = g.nbh * g.nbt * g.nbr;
     int bid = blockIdx.x;
@@ -897,7 +899,8 @@ static size_t table_bytes(const GeomDev &g) {
 }
 
 static size_t bp_lds_bytes(const GeomDev &g, bool sart) {
-    return table_bytes(g) + 4 * sizeof(float) * (size_t)(g.bh * (g.bt * (g.br + 1) + 1) + 1) * (sart ? 2 : 1);
+    return sizeof(float2) * (size_t)(g.n_theta + 1) +
+           4 * sizeof(float) * (size_t)(g.bh * (g.bt * (g.br + 1) + 1) + 1) * (sart ? 2 : 1);
 }
 
 // Rays per launch below which each ray is split over neighbouring lanes so one
