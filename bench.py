@@ -23,6 +23,24 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch (read + written) of the FP32 SART kernels on this
+# workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE passes scaled by a 1 GiB
+# device copy, taken on the kernel sources whose sha256 prefix is given here
+# (profiles/fp_bp_sart_single_256x720x128_hbm_counters.md). For any other
+# source, or another storage type, the traffic is reported as null.
+MEASURED_TRAFFIC = {"src_sha": "b5e7e36be6274ecb",
+                    "fp_residual": 108210227 + 1529859,
+                    "bp_update": 189096711 + 93193984}
+
+
+def kernel_src_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("cyl_kernels.hip", "cyl_host.cpp", "cyl_internal.h"):
+        with open(os.path.join(ROOT, "paper_2005_11976_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -154,6 +172,9 @@ def main():
     dom_bytes = bp_bytes if dom == "bp_update" else fp_bytes
     dom_ms = max(bp_ms, fp_ms)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    traffic = None
+    if args.dtype == "f32" and kernel_src_sha() == MEASURED_TRAFFIC["src_sha"]:
+        traffic = MEASURED_TRAFFIC[dom]
     iter_bytes = scan.n_views * (fp_bytes + bp_bytes)
     path_gbs = iter_bytes * it_s / 1e9
 
@@ -194,7 +215,7 @@ def main():
         "path_hbm_frac": path_gbs / HBM_PEAK_GBS,
         "kernel_ms": {"fp_residual": fp_ms, "bp_update": bp_ms},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": dom_bytes},
         "cpu_baseline": cpu,
         "rel_err_vs_truth": rel_truth,
