@@ -59,7 +59,9 @@ enum {
 };
 
 /* Cylindrical grid in the object frame (Sec. 2, Eq. 2).
- * Requires n_h, n_theta, n_r >= 1, 0 <= r_min < r_max, h_min < h_max. */
+ * Requires n_h, n_theta, n_r >= 1, 0 <= r_min < r_max, h_min < h_max, at most
+ * 2^30 - 1 cells (volume byte offsets are 32-bit) and n_theta * n_r < 2^24
+ * (cell indices are formed with 24-bit products). */
 typedef struct {
     int32_t n_h, n_theta, n_r;
     double r_min, r_max;

@@ -87,8 +87,9 @@ extern "C" int cyl_geom_create(const cyl_grid *grid, const cyl_traj *traj, const
         set_error("cyl_geom_create: grid sizes must be >= 1 (got %d x %d x %d)", g.n_h, g.n_theta, g.n_r);
         return CYL_EINVAL;
     }
-    if ((int64_t)g.n_h * g.n_theta * g.n_r > (int64_t)INT32_MAX) {
-        set_error("cyl_geom_create: grid has more than 2^31-1 cells");
+    if ((int64_t)g.n_h * g.n_theta * g.n_r >= ((int64_t)1 << 30) || (int64_t)g.n_theta * g.n_r >= (1 << 24)) {
+        set_error("cyl_geom_create: grid of %d x %d x %d cells exceeds 2^30 - 1 cells or n_theta * n_r >= 2^24",
+                  g.n_h, g.n_theta, g.n_r);
         return CYL_EINVAL;
     }
     if (!(std::isfinite(g.r_min) && std::isfinite(g.r_max) && std::isfinite(g.h_min) &&

@@ -39,29 +39,50 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 
 template <int DT>
 struct Store;
+// ld/st: plain global access.  ldb: load element i through a buffer resource
+// (32-bit offsets, range-checked by the hardware: an offset past the end reads
+// 0), used for the gathers of the traversal.
 template <>
 struct Store<CYL_F32> {
+    static constexpr int kSize = 4;
     static __device__ __forceinline__ float ld(const void *p, size_t i) { return ((const float *)p)[i]; }
     static __device__ __forceinline__ void st(void *p, size_t i, float v) { ((float *)p)[i] = v; }
+    static __device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t rs, unsigned i) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, i << 2, 0, 0));
+    }
 };
 template <>
 struct Store<CYL_F16> {
+    static constexpr int kSize = 2;
     static __device__ __forceinline__ float ld(const void *p, size_t i) {
         return __half2float(((const __half *)p)[i]);
     }
     static __device__ __forceinline__ void st(void *p, size_t i, float v) {
         ((__half *)p)[i] = __float2half_rn(v);
     }
+    static __device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t rs, unsigned i) {
+        const unsigned short x = __builtin_amdgcn_raw_buffer_load_b16(rs, i << 1, 0, 0);
+        return __half2float(__builtin_bit_cast(__half, x));
+    }
 };
 template <>
 struct Store<CYL_BF16> {
+    static constexpr int kSize = 2;
     static __device__ __forceinline__ float ld(const void *p, size_t i) {
         return bf16_to_f32(((const uint16_t *)p)[i]);
     }
     static __device__ __forceinline__ void st(void *p, size_t i, float v) {
         ((uint16_t *)p)[i] = f32_to_bf16(v);
     }
+    static __device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t rs, unsigned i) {
+        return bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(rs, i << 1, 0, 0));
+    }
 };
+
+// Buffer resource over n bytes at p (gfx9 word 3: 32-bit data format).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *p, unsigned nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)nbytes, 0x00020000);
+}
 
 // Load of a runtime-typed optional array (weights); the switch is uniform.
 __device__ __forceinline__ float ld_any(const void *p, int dt, size_t i) {
@@ -71,6 +92,25 @@ __device__ __forceinline__ float ld_any(const void *p, int dt, size_t i) {
 }
 
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// min / max of loop-carried values without the canonicalising moves the
+// compiler otherwise inserts before every v_min/v_max (the operands are never
+// signalling NaNs: they come from arithmetic or are +inf)
+__device__ __forceinline__ float vmin3(float a, float b, float c) {
+    float d;
+    asm("v_min3_f32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+__device__ __forceinline__ float vmin(float a, float b) {
+    float d;
+    asm("v_min_f32 %0, %1, %2" : "=v"(d) : "v"(a), "v"(b));
+    return d;
+}
+__device__ __forceinline__ float vmax(float a, float b) {
+    float d;
+    asm("v_max_f32 %0, %1, %2" : "=v"(d) : "v"(a), "v"(b));
+    return d;
+}
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // ------------------------------------------------------------ grid tables
@@ -332,16 +372,6 @@ __device__ __forceinline__ void cell_at(const GeomDev &g, const RayF &r, float s
 
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
-// Next sector-edge crossing after s through edge b (cs = its cos, sin).  An
-// edge-half-line meeting behind s means the start cell was one sector short
-// (rounding at entry): cross it at once.
-__device__ __forceinline__ float t_cand(const GeomDev &g, const ViewDev &V, const RayF &r, int dir_t, float2 cs,
-                                        int b, float s, bool refine = true) {
-    if (r.flags & RAY_THRU) return s < 0.0f ? 0.0f : CYL_INF;
-    const EdgeX x = edge_cross(g, V, r, cs, b, refine);
-    return (dir_t != 0 && x.on_edge) ? fmaxf(x.s, s) : CYL_INF;
-}
-
 // Shell and plane offsets of a ray, rebased at the shell nearest to b and the
 // plane nearest to z_c:  r_i - b = (i - ic) dr + (r_ic - b) and
 // h_m - z_c = (m - mc) dh + (h_mc - z_c), with dr, dh as two FP32 words, so
@@ -363,78 +393,145 @@ __device__ __forceinline__ Rebase rebase(const GeomDev &g, const Tabs &T, const 
     return q;
 }
 
-// r_i - b
-__device__ __forceinline__ float shell_off(const GeomDev &g, const Rebase &q, int i) {
-    const float k = (float)(i - q.ic);
-    return fmaf(k, g.dr, fmaf(k, g.dr_lo, q.drc));
+// Index box of a walk: it ends as soon as an index leaves [lo, lo + n).
+struct Box {
+    int hlo, hn, tlo, tn, rlo, rn;
+};
+
+// Per-ray constants of the walk.
+//  planes: s_m = k zA + (k zAlo + zB), k = m - mc, i.e. (h_m - z_c) / e_z with
+//    the products by 1/e_z taken once per ray (zB = +inf for level rays);
+//  shells: d_i = r_i - b = k dr + (k dr_lo + drc), k = i - ic (drc = +inf for
+//    rays parallel to the axis, which cross no shell); ib is the innermost
+//    shell the ray reaches (r_ib > b), so the next shell before the closest
+//    approach is r_ir if ir >= ib, else the ray turns and leaves through
+//    r_{ir+1};
+//  sector edges: with (cx, cy, ex, ey) multiplied by the sweep direction, the
+//    edge's half-line is met ahead iff n.e > 0 (e_xy is perpendicular to c, so
+//    n.e = +-|e_xy| (m.c)/b with m the edge direction), at s = -(n.c)/(n.e).
+struct Walk {
+    float zA, zAlo, zB;
+    int kz, dir_h;
+    float drc, twob;
+    int ic, ib;
+    float tcx, tcy, tex, tey;
+    int dir_t, up_t, tstep, twrap;
+};
+
+__device__ __forceinline__ Walk walk_setup(const GeomDev &g, const Tabs &T, const RayF &r, int it) {
+    const Rebase q = rebase(g, T, r);
+    Walk w;
+    w.dir_h = r.ez > 0.0f ? 1 : (r.ez < 0.0f ? -1 : 0);
+    if (w.dir_h != 0) {
+        w.zA = g.dh * r.inv_ez;
+        w.zAlo = g.dh_lo * r.inv_ez;
+        w.zB = q.dzc * r.inv_ez;
+    } else {
+        w.zA = w.zAlo = 0.0f;
+        w.zB = CYL_INF;
+    }
+    w.kz = (w.dir_h > 0 ? 1 : 0) - q.mc;
+    w.ic = q.ic;
+    w.ib = (r.flags & RAY_AXIAL) ? 0x7fffffff : q.ic + (q.drc > 0.0f ? 0 : 1);
+    w.drc = (r.flags & RAY_AXIAL) ? CYL_INF : q.drc;
+    w.twob = 2.0f * r.b;
+    const float cross = r.cx * r.ey - r.cy * r.ex;
+    const int nt = g.n_theta;
+    w.dir_t = (nt == 1 || (r.flags & (RAY_AXIAL | RAY_THRU))) ? 0 : (cross > 0.0f ? 1 : (cross < 0.0f ? -1 : 0));
+    w.up_t = w.dir_t > 0 ? 1 : 0;
+    // a ray through the axis jumps from the start sector to the one ahead
+    w.tstep = (r.flags & RAY_THRU) ? r.it_out - it : w.dir_t;
+    w.twrap = w.dir_t * nt;
+    const float sg = w.dir_t < 0 ? -1.0f : 1.0f;
+    w.tcx = sg * r.cx;
+    w.tcy = sg * r.cy;
+    w.tex = sg * r.ex;
+    w.tey = sg * r.ey;
+    return w;
 }
 
-// Crossing parameter of axial plane m.
-__device__ __forceinline__ float plane_at(const GeomDev &g, const Rebase &q, const RayF &r, int m) {
-    const float k = (float)(m - q.mc);
-    return fmaf(k, g.dh, fmaf(k, g.dh_lo, q.dzc)) * r.inv_ez;
-}
-
-// Next shell crossing after s for ring ir: inward through r_ir while before
-// the closest approach and the ray reaches it, else outward through r_{ir+1}.
-__device__ __forceinline__ float r_cand(const GeomDev &g, const Rebase &q, const RayF &r, int ir, float s,
-                                        int &r_dir) {
-    const float dl = shell_off(g, q, ir);
-    const float du = shell_off(g, q, ir + 1);
-    const bool inward = (s < 0.0f) && (ir >= 0) && (dl > 0.0f);
-    const float d = fmaxf(inward ? dl : du, 0.0f);
-    const float w = fsqrt(d * (d + 2.0f * r.b)) * r.inv_k;
+// Next shell crossing after s from ring ir (not clamped to s).
+__device__ __forceinline__ float shell_next(const GeomDev &g, const Walk &w, const RayF &r, int ir, float s,
+                                            int &r_dir) {
+    const bool inward = (s < 0.0f) && (ir >= w.ib);
+    const float k = (float)((inward ? ir : ir + 1) - w.ic);
+    const float d = fmaxf(fmaf(k, g.dr, fmaf(k, g.dr_lo, w.drc)), 0.0f);
+    const float x = fsqrt(d * (d + w.twob)) * r.inv_k;
     r_dir = inward ? -1 : 1;
-    return (r.flags & RAY_AXIAL) ? CYL_INF : fmaxf(inward ? -w : w, s);
+    return inward ? -x : x;
+}
+
+// Crossing of plane m = ih + (dir_h > 0).
+__device__ __forceinline__ float plane_next(const Walk &w, int ih) {
+    const float k = (float)(ih + w.kz);
+    return fmaf(k, w.zA, fmaf(k, w.zAlo, w.zB));
+}
+
+// Crossing of sector edge be (cs = its cos, sin) ahead of s, or +inf.  An
+// edge-half-line meeting behind s means the start cell was one sector short
+// (rounding at entry): cross it at once.  Near-parallel cases (|n.e| below
+// kEdgeTau) are re-solved in FP64 when `refine` is set.
+__device__ __forceinline__ float edge_next(const ViewDev &V, const GeomDev &g, const Walk &w, const RayF &r,
+                                           float2 cs, int be, float s, bool refine) {
+    const float nc = cs.x * w.tcy - cs.y * w.tcx;
+    const float ne = cs.x * w.tey - cs.y * w.tex;
+    float x = -nc * frcp(ne);
+    bool ahead = ne > 0.0f;
+    if (refine && w.dir_t != 0 && fabsf(ne) < kEdgeTau) {
+        EdgeX e;
+        edge_cross_fp64(g.cs64[be], &V, r.pix, r.len, &e);
+        x = e.s;
+        ahead = e.on_edge;
+    }
+    return (w.dir_t != 0 && ahead) ? vmax(x, s) : CYL_INF;
 }
 
 // Walk the ray from s to s_end starting in cell (ih, it, ir) and call
 // visit(ih, it, ir, length) for every piece (length 0 allowed; ir = -1 is the
 // hole), and visit.late() at the end of each step (and once after the walk)
-// for work the visitor wants to spread out.  Each step computes the three next-crossing candidates with selects
-// (no divergent branch but the rare FP64 edge case); shell and plane
-// crossings are arithmetic, so the only table read per step is the next
-// sector edge.  The visitor runs before the index updates so a gather it
-// issues overlaps them.
-template <class Visit>
+// for work the visitor wants to spread out.  The walk also ends when an index
+// leaves the box bx.  Each step takes the nearest of the three next-crossing
+// candidates and recomputes the candidate of that kind with selects (no
+// divergent branch but the rare FP64 edge case); shell and plane crossings are
+// arithmetic, so the only table read per step is the next sector edge, issued
+// before the visitor so that its latency overlaps the visitor's work.  Plane
+// and shell candidates after their own event are monotone in the index, so
+// only the first ones and the edge candidates are clamped to s.
+template <bool CHECK_T, class Visit>
 __device__ __forceinline__ void traverse(const GeomDev &g, const Tabs &T, const ViewDev &V, const RayF &r, float s,
-                                         const float s_end, int ih, int it, int ir, Visit &visit) {
-    const int nh = g.n_h, nr = g.n_r, nt = g.n_theta;
-    const int dir_h = r.ez > 0.0f ? 1 : (r.ez < 0.0f ? -1 : 0);
-    const float cross = r.cx * r.ey - r.cy * r.ex;
-    const int dir_t = (nt == 1 || (r.flags & (RAY_AXIAL | RAY_THRU))) ? 0 : (cross > 0.0f ? 1 : (cross < 0.0f ? -1 : 0));
-    const int up_t = dir_t > 0 ? 1 : 0;
-    const int up_h = dir_h > 0 ? 1 : 0;
-    const Rebase q = rebase(g, T, r);
+                                         const float s_end, int ih, int it, int ir, const Box &bx, Visit &visit) {
+    const int nt = g.n_theta;
+    const Walk w = walk_setup(g, T, r, it);
     int r_dir;
-    float s_z = dir_h != 0 ? fmaxf(plane_at(g, q, r, ih + up_h), s) : CYL_INF;
-    float s_r = r_cand(g, q, r, ir, s, r_dir);
-    float s_t = (nt == 1) ? CYL_INF : t_cand(g, V, r, dir_t, T.cs[it + up_t], it + up_t, s);
-    const int max_steps = 2 * nr + nt + nh + 8;
+    float s_z = fmaxf(plane_next(w, ih), s);
+    float s_r = fmaxf(shell_next(g, w, r, ir, s, r_dir), s);
+    float s_t;
+    if (r.flags & RAY_THRU)
+        s_t = s < 0.0f ? 0.0f : CYL_INF;
+    else
+        s_t = edge_next(V, g, w, r, T.cs[it + w.up_t], it + w.up_t, s, true);
+    const int max_steps = 2 * g.n_r + nt + g.n_h + 8;
     for (int n = 0; n < max_steps; ++n) {
-        const float sn = fminf(fminf(s_z, s_r), fminf(s_t, s_end));
+        const float sn = vmin(vmin3(s_z, s_r, s_t), s_end);
         const bool ev_z = (sn == s_z);
         const bool ev_r = !ev_z && (sn == s_r);
         const bool ev_t = !ev_z && !ev_r;
-        const int nih = ih + (ev_z ? dir_h : 0);
-        const int nir = ir + (ev_r ? r_dir : 0);
-        int itn = it + (ev_t ? dir_t : 0);
-        itn = itn < 0 ? itn + nt : (itn >= nt ? itn - nt : itn);
-        const int nit = (ev_t && (r.flags & RAY_THRU)) ? r.it_out : itn;
-        // read the next sector edge before the visitor's LDS atomics, so that
-        // waiting for it does not wait for them (LDS operations retire in order)
-        const int be = nit + up_t;
+        int itn = it + (ev_t ? w.tstep : 0);
+        itn -= ((unsigned)itn >= (unsigned)nt) ? w.twrap : 0;
+        const int be = itn + w.up_t;
         const float2 cse = T.cs[be];
         visit(ih, it, ir, sn - s);
         s = sn;
-        ih = nih;
-        ir = nir;
-        it = nit;
-        if (!(sn < s_end) || (unsigned)ih >= (unsigned)nh || ir >= nr) break;
+        ih += ev_z ? w.dir_h : 0;
+        ir += ev_r ? r_dir : 0;
+        it = itn;
+        if (!(sn < s_end) || (unsigned)(ih - bx.hlo) >= (unsigned)bx.hn ||
+            (unsigned)(ir - bx.rlo) >= (unsigned)bx.rn || (CHECK_T && (unsigned)(it - bx.tlo) >= (unsigned)bx.tn))
+            break;
         int rd;
-        const float nz = dir_h != 0 ? fmaxf(plane_at(g, q, r, ih + up_h), s) : CYL_INF;
-        const float nrr = r_cand(g, q, r, ir, s, rd);
-        const float ntt = t_cand(g, V, r, dir_t, cse, be, s, ev_t);
+        const float nz = plane_next(w, ih);
+        const float nrr = shell_next(g, w, r, ir, s, rd);
+        const float ntt = edge_next(V, g, w, r, cse, be, s, ev_t);
         s_z = ev_z ? nz : s_z;
         s_r = ev_r ? nrr : s_r;
         r_dir = ev_r ? rd : r_dir;
@@ -451,7 +548,7 @@ __device__ __forceinline__ void traverse(const GeomDev &g, const Tabs &T, const 
 // one ray can run on neighbouring lanes.
 template <int VT>
 __device__ __forceinline__ float fp_piece(const GeomDev &g, const Tabs &T, const ViewDev &V, const RayF &r,
-                                          const void *__restrict__ vol, int piece, int npieces) {
+                                          __amdgpu_buffer_rsrc_t vol, int piece, int npieces) {
     if (!(r.flags & RAY_HIT)) return 0.0f;
     const float span = (r.s_out - r.s_in) / (float)npieces;
     const float a0 = piece == 0 ? r.s_in : fmaf((float)piece, span, r.s_in);
@@ -459,23 +556,26 @@ __device__ __forceinline__ float fp_piece(const GeomDev &g, const Tabs &T, const
     if (!(a1 > a0)) return 0.0f;
     int ih, it, ir;
     cell_at(g, r, a0, ih, it, ir);
-    const int nt = g.n_theta, nr = g.n_r;
-    // the gather of one step is consumed in the next, so its latency overlaps a
-    // whole traversal step
+    // the gather of one step is consumed at the start of the next (before the
+    // next gather is issued, so the two share a register and the wait for the
+    // load falls a whole step later); cell indices fit in 24-bit products
+    // (checked when the geometry is created)
     struct Gather {
-        const void *vol;
-        int nt, nr;
+        __amdgpu_buffer_rsrc_t vol;
+        int nt, nr, ntr;
         float acc, plen, pval;
         __device__ __forceinline__ void operator()(int h, int t, int q, float len) {
-            const int idx = (h * nt + t) * nr + (q < 0 ? 0 : q);
-            const float val = Store<VT>::ld(vol, (size_t)idx);
-            acc = fmaf(plen, pval, acc);
+            const unsigned idx = __umul24(h, ntr) + __umul24(t, nr) + (q < 0 ? 0 : q);
+            // kept in place (volatile) so the compiler neither sinks it to the end
+            // of the step nor copies the loaded value
+            asm volatile("v_fmac_f32 %0, %1, %2" : "+v"(acc) : "v"(plen), "v"(pval));
+            pval = Store<VT>::ldb(vol, idx);
             plen = q < 0 ? 0.0f : len;
-            pval = val;
         }
         __device__ __forceinline__ void late() {}
-    } visit{vol, nt, nr, 0.0f, 0.0f, 0.0f};
-    traverse(g, T, V, r, a0, a1, ih, it, ir, visit);
+    } visit{vol, g.n_theta, g.n_r, g.n_theta * g.n_r, 0.0f, 0.0f, 0.0f};
+    const Box bx{0, g.n_h, 0, g.n_theta, -1, g.n_r + 1};
+    traverse<false>(g, T, V, r, a0, a1, ih, it, ir, bx, visit);
     return fmaf(visit.plen, visit.pval, visit.acc);
 }
 
@@ -512,7 +612,9 @@ __global__ __launch_bounds__(256) void fp_kernel(GeomDev g, const void *__restri
     double dx, dy, dz, tc;
     ray_geom(g, T, V, live ? u : 0, live ? v : 0, r, dx, dy, dz, tc);
     if (!live) r.flags = 0;
-    float acc = fp_piece<VT>(g, T, V, r, vol, piece, nsplit);
+    const __amdgpu_buffer_rsrc_t vrs =
+        buffer_rsrc(vol, (unsigned)g.n_h * (unsigned)g.n_theta * (unsigned)g.n_r * (unsigned)Store<VT>::kSize);
+    float acc = fp_piece<VT>(g, T, V, r, vrs, piece, nsplit);
     if (nsplit > 1) {
         part[threadIdx.x] = acc;
         __syncthreads();
@@ -726,7 +828,6 @@ __device__ __forceinline__ int block_slots(const Block &B) { return slot(B, B.hB
 template <bool COLSUM>
 __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const ViewDev &V, const Block &B, int u,
                                        int v, float yj, float *acc_c, int *acc_n, float nscale) {
-    const int spare = block_slots(B) - 1;
     RayF r;
     double dx, dy, dz, tc;
     ray_geom(g, T, V, u, v, r, dx, dy, dz, tc);
@@ -752,26 +853,31 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Vi
     // c accumulates with a float LDS atomic.  The column sum n, which depends on
     // the geometry only, accumulates in fixed point with an integer LDS atomic
     // (far cheaper than a second float atomic on gfx950), issued at the end of
-    // the step; nscale bounds the sum below 2^31 (see bp_kernel).
+    // the step; nscale bounds the sum below 2^31 (see bp_kernel).  The walk is
+    // boxed to the block, so every visited cell has a slot:
+    // slot = h ps + t rs + q - (hA ps + tA rs + rA), folded into the bases.
+    const int rs = (B.rB - B.rA) + 1;
+    const int ps = (B.tB - B.tA) * rs + 1;
+    const int off = B.hA * ps + B.tA * rs + B.rA;
     struct Scatter {
-        const Block &B;
-        float *acc_c;
-        int *acc_n;
+        float *cb;
+        int *nb;
+        int ps, rs;
         float yj, nscale;
-        int spare, nloc;
+        int nloc;
         float nlen;
         __device__ __forceinline__ void operator()(int h, int t, int q, float len) {
-            const bool in = q >= B.rA && q < B.rB && h >= B.hA && h < B.hB && t >= B.tA && t < B.tB;
-            const int loc = in ? slot(B, h - B.hA, t - B.tA, q - B.rA) : spare;
-            atomicAdd(&acc_c[loc], len * yj);
+            const int loc = (int)(__umul24(h, ps) + __umul24(t, rs)) + q;
+            atomicAdd(&cb[loc], len * yj);
             nloc = loc;
             nlen = len;
         }
         __device__ __forceinline__ void late() {
-            if (COLSUM && nlen != 0.0f) atomicAdd(&acc_n[nloc], __float2int_rn(nlen * nscale));
+            if (COLSUM && nlen != 0.0f) atomicAdd(&nb[nloc], __float2int_rn(nlen * nscale));
             nlen = 0.0f;
         }
-    } visit{B, acc_c, acc_n, yj, nscale, spare, spare, 0.0f};
+    } visit{acc_c - off, acc_n - off, ps, rs, yj, nscale, 0, 0.0f};
+    const Box bx{B.hA, B.hB - B.hA, B.tA, B.tB - B.tA, B.rA, B.rB - B.rA};
     for (int piece = 0; piece < 2; ++piece) {
         const float a0 = piece ? pb0 : pa0, a1 = piece ? pb1 : pa1;
         if (!(a1 > a0)) continue;
@@ -787,7 +893,7 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Vi
             if (dhi < 0) dhi += g.n_theta;
             it = dlo <= dhi ? B.tA : B.tB - 1;
         }
-        traverse(g, T, V, r, a0, a1, ih, it, ir, visit);
+        traverse<true>(g, T, V, r, a0, a1, ih, it, ir, bx, visit);
     }
 }
 
