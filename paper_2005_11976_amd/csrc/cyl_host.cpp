@@ -2,6 +2,7 @@
 // applied once per view), grid tables, error reporting.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -224,13 +225,43 @@ extern "C" int cyl_geom_create(const cyl_grid *grid, const cyl_traj *traj, const
         }
     cs64[g.n_theta] = cs64[0];
     cs[g.n_theta] = cs[0];
+    // forward-projection dispatch orders (pieces per ray 1, 2, 4: tiles 32, 16,
+    // 8 pixels wide by 8 high).  Workgroups go round-robin to the 8 XCDs; XCD x
+    // receives a contiguous run of row-major tiles (a band of rows, so its L2
+    // holds one band of the volume) in centre-out column order: the central
+    // columns carry the longest rays, so dispatching them first leaves the
+    // short edge tiles for the tail of the launch.
+    std::vector<int32_t> fpo[3];
+    for (int i = 0; i < 3; ++i) {
+        const int tw = 8 * (4 >> i);  // pieces per ray 1 << i
+        const int tu = (W + tw - 1) / tw, tv = (H + 7) / 8;
+        const int total = tu * tv;
+        fpo[i].assign(total, 0);
+        int start = 0;
+        for (int x = 0; x < 8; ++x) {
+            const int n = total / 8 + (x < total % 8 ? 1 : 0);
+            std::vector<int32_t> list(n);
+            for (int k = 0; k < n; ++k) list[k] = start + k;
+            std::stable_sort(list.begin(), list.end(), [tu](int32_t a, int32_t b) {
+                const double da = std::fabs(a % tu + 0.5 - 0.5 * tu), db = std::fabs(b % tu + 0.5 - 0.5 * tu);
+                return da < db;
+            });
+            for (int k = 0; k < n; ++k) fpo[i][x + 8 * k] = list[k];
+            start += n;
+        }
+    }
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t off_views = 0;
     size_t off_r = align(off_views + sizeof(ViewDev) * nv);
     size_t off_h = align(off_r + sizeof(float2) * rt.size());
     size_t off_cs = align(off_h + sizeof(float2) * ht.size());
     size_t off_cs64 = align(off_cs + sizeof(float2) * cs.size());
+    size_t off_fpo[3];
     size_t total = align(off_cs64 + sizeof(double2) * cs64.size());
+    for (int i = 0; i < 3; ++i) {
+        off_fpo[i] = total;
+        total = align(total + sizeof(int32_t) * fpo[i].size());
+    }
     void *dmem = nullptr;
     if ((e = hipMalloc(&dmem, total)) != hipSuccess) {
         hipSetDevice(prev);
@@ -243,6 +274,9 @@ extern "C" int cyl_geom_create(const cyl_grid *grid, const cyl_traj *traj, const
               hipMemcpy(base + off_h, ht.data(), sizeof(float2) * ht.size(), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(base + off_cs, cs.data(), sizeof(float2) * cs.size(), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(base + off_cs64, cs64.data(), sizeof(double2) * cs64.size(), hipMemcpyHostToDevice) == hipSuccess;
+    for (int i = 0; i < 3 && ok; ++i)
+        ok = hipMemcpy(base + off_fpo[i], fpo[i].data(), sizeof(int32_t) * fpo[i].size(), hipMemcpyHostToDevice) ==
+             hipSuccess;
     if (!ok) {
         hipFree(dmem);
         hipSetDevice(prev);
@@ -289,6 +323,7 @@ extern "C" int cyl_geom_create(const cyl_grid *grid, const cyl_traj *traj, const
     d.h_tab = (const float2 *)(base + off_h);
     d.cs_tab = (const float2 *)(base + off_cs);
     d.cs64 = (const double2 *)(base + off_cs64);
+    for (int i = 0; i < 3; ++i) d.fp_order[i] = (const int32_t *)(base + off_fpo[i]);
     // back-projection blocks: flat in h, wide in theta and r; wedges no wider than pi
     d.bh = g.n_h < 4 ? g.n_h : 4;
     d.br = g.n_r < 16 ? g.n_r : 16;

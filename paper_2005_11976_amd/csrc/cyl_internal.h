@@ -34,6 +34,9 @@ struct GeomDev {
     const float2 *cs_tab;  // n_theta + 1 sector edges as (cos, sin)
     const double2 *cs64;   // the same in FP64 (ill-conditioned crossings)
     const ViewDev *views;  // n_views
+    // forward-projection dispatch order for 1, 2 and 4 pieces per ray:
+    // fp_order[i][blockIdx.x] = pixel tile (row-major over tiles)
+    const int32_t *fp_order[3];
     // back-projection block decomposition (cells per block along h, theta, r)
     int32_t bh, bt, br;
     int32_t nbh, nbt, nbr;

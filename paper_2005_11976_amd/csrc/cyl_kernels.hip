@@ -583,9 +583,8 @@ __device__ __forceinline__ float fp_piece(const GeomDev &g, const Tabs &T, const
 // workgroup covers 256 / nsplit rays; wave w takes piece w % nsplit of the
 // 64 rays of pixel group w / nsplit (an 8 x 8 tile), so the lanes of a wave
 // walk the same stretch of neighbouring rays and their gathers stay coherent.
-// Partial sums meet in LDS.  blockIdx.y = view offset.  Tiles are dealt so
-// that each XCD (blocks go round-robin to the 8 XCDs) gets a contiguous band
-// of rows.
+// Partial sums meet in LDS.  blockIdx.y = view offset; blockIdx.x indexes the
+// geometry's dispatch order (per-XCD row bands, centre-out columns).
 template <int VT, int PT, bool SART>
 __global__ __launch_bounds__(256) void fp_kernel(GeomDev g, const void *__restrict__ vol, void *__restrict__ proj,
                                                  int view_begin, int nsplit, const void *__restrict__ pw, int pwt,
@@ -601,9 +600,7 @@ __global__ __launch_bounds__(256) void fp_kernel(GeomDev g, const void *__restri
     // workgroup tile: 8 * groups wide, 8 high
     const int tw = 8 * groups;
     const int tiles_u = (g.cols + tw - 1) / tw;
-    const int ntiles = tiles_u * ((g.rows + 7) / 8);
-    int tile = blockIdx.x;
-    if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
+    const int tile = g.fp_order[nsplit == 1 ? 0 : (nsplit == 2 ? 1 : 2)][blockIdx.x];
     const int u = (tile % tiles_u) * tw + grp * 8 + (lane & 7);
     const int v = (tile / tiles_u) * 8 + (lane >> 3);
     const bool live = u < g.cols && v < g.rows;
@@ -913,13 +910,17 @@ __global__ __launch_bounds__(256) void bp_kernel(GeomDev g, const void *__restri
     const int slots = g.bh * (g.bt * (g.br + 1) + 1) + 1;
     float *acc_c = (float *)(smem + table_floats2(g, false)) + wave * slots * (MODE == 1 ? 2 : 1);
     int *acc_n = (int *)(acc_c + slots);
-    const int nblk = g.nbh * g.nbt * g.nbr;
-    int bid = blockIdx.x;
-    const int ngroups = gridDim.x;
-    if ((ngroups & 7) == 0) bid = (blockIdx.x & 7) * (ngroups >> 3) + (blockIdx.x >> 3);
-    const int b = bid * 4 + wave;
-    const bool live = b < nblk;
-    const Block B = block_of(g, live ? b : 0);
+    // dispatch order: outer rings first (their blocks carry the most work), and
+    // the 4 waves of a workgroup take 4 blocks stacked in h (similar work, so
+    // the workgroup's LDS is not held by one slow wave)
+    const int nhg = (g.nbh + 3) / 4;
+    const int per_ring = g.nbt * nhg;
+    const int ibr = g.nbr - 1 - (int)blockIdx.x / per_ring;
+    const int rem = (int)blockIdx.x % per_ring;
+    const int ibh = (rem % nhg) * 4 + wave;
+    const bool live = ibh < g.nbh;
+    const int b = ((live ? ibh : 0) * g.nbt + rem / nhg) * g.nbr + ibr;
+    const Block B = block_of(g, b);
     const int wt = B.tB - B.tA, wr = B.rB - B.rA;
     const int ncell = (B.hB - B.hA) * wt * wr;
     const int nslot = block_slots(B);
@@ -1055,8 +1056,7 @@ template <int VT, int PT>
 static void launch_bp_t(const cyl_geom *G, const void *y, int vb, int ve, void *vol, int accumulate, bool sart,
                         const float *rho, const void *vw, int vwt, float lam, int nonneg, hipStream_t st) {
     const GeomDev &g = G->dev;
-    const int nblk = g.nbh * g.nbt * g.nbr;
-    dim3 grid((nblk + 3) / 4);
+    dim3 grid(g.nbr * g.nbt * ((g.nbh + 3) / 4));
     const size_t lds = bp_lds_bytes(g, sart);
     if (sart)
         hipLaunchKernelGGL((bp_kernel<VT, PT, 1>), grid, dim3(256), lds, st, g, y, vb, ve, vol, accumulate, rho, vw,
