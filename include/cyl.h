@@ -177,6 +177,41 @@ int cyl_sart_update(const cyl_geom *geom, int32_t view, double lambda, int32_t n
                     const void *vox_weights, cyl_dtype vox_weights_type, void *vol, cyl_dtype vol_type,
                     const void *workspace, size_t workspace_bytes, void *hip_stream);
 
+/* One SART sub-iteration (Eq. 7 with the ordered subset = one projection,
+ * Sec. 2.2) for each of n independent scans, in two launches: the forward
+ * projections with residuals of all items, then their back-projections with
+ * updates.  Serving uses it to run scans that arrive over time side by side
+ * (different grids, poses and detectors); item i computes exactly what
+ * cyl_sart_residual(view) + cyl_sart_update(view) compute for it alone, bit for
+ * bit, whatever else is in the batch.
+ *   items[i].geom       geometry of scan i; all geometries on one device
+ *   items[i].view       view of this sub-iteration, in [0, n_views)
+ *   items[i].proj       measured projections of scan i, all views, proj_type
+ *   items[i].proj_weights / vox_weights   per-pixel / per-voxel weights or NULL
+ *   items[i].vol        volume of scan i, updated in place, vol_type
+ *   items[i].workspace  >= cyl_sart_workspace_bytes(geom) bytes of device memory
+ * Storage types are common to the batch.  Volumes and workspaces of different
+ * items must not overlap (they are written concurrently).  n = 0 is a no-op;
+ * any n >= 1 is accepted (launched in groups of 16 items).  Errors: CYL_EINVAL
+ * for a NULL items array or field, a view out of range, a small workspace,
+ * mixed devices or a non-finite lambda (nothing enqueued). */
+typedef struct {
+    const cyl_geom *geom;
+    int32_t view;
+    const void *proj;
+    const void *proj_weights;
+    const void *vox_weights;
+    void *vol;
+    void *workspace;
+    size_t workspace_bytes;
+    double lambda;
+    int32_t nonneg;
+} cyl_sart_batch_item;
+
+int cyl_sart_batch_step(int32_t n, const cyl_sart_batch_item *items, cyl_dtype proj_type,
+                        cyl_dtype proj_weights_type, cyl_dtype vox_weights_type, cyl_dtype vol_type,
+                        void *hip_stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *cyl_last_error(void);
 

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <vector>
@@ -541,6 +542,42 @@ __device__ __forceinline__ void traverse(const GeomDev &g, const Tabs &T, const 
     visit.late();
 }
 
+// ------------------------------------------------------------ launch items
+
+// One launch covers up to kMaxBatch items, each a scan (its geometry, buffers
+// and views); blockIdx.y selects the item.  A single call is a launch of one
+// item, a batched SART step one item per scan, so every path runs the same
+// kernels.  The items travel in the kernel arguments (read with scalar loads,
+// uniform across the workgroup), which bounds a launch to 16 items.
+constexpr int kMaxBatch = 16;
+
+struct FpItem {
+    GeomDev g;
+    const void *vol;      // volume (storage type VT)
+    void *proj;           // projections: output (plain) or measured data (SART)
+    const void *pw;       // projection weights or null (SART)
+    float *rho;           // residual image of the view (SART)
+    int view, ns, nwg, pwt;  // view, pieces per ray, workgroups, weight type
+};
+struct FpLaunch {
+    int n;
+    FpItem item[kMaxBatch];
+};
+
+struct BpItem {
+    GeomDev g;
+    const void *y;        // projections (plain) or FP32 residual image (SART)
+    void *vol;
+    const void *vw;       // voxel weights or null (SART)
+    int view_begin, view_end, nwg, accumulate, vwt, nonneg;
+    float lam;
+};
+struct BpLaunch {
+    int n;
+    BpItem item[kMaxBatch];
+};
+static_assert(sizeof(FpLaunch) <= 4096 && sizeof(BpLaunch) <= 4096, "kernel arguments are limited to 4 KiB");
+
 // ------------------------------------------------------------ forward projection
 
 // Partial forward projection of piece `piece` of `npieces` equal parameter
@@ -583,17 +620,24 @@ __device__ __forceinline__ float fp_piece(const GeomDev &g, const Tabs &T, const
 // workgroup covers 256 / nsplit rays; wave w takes piece w % nsplit of the
 // 64 rays of pixel group w / nsplit (an 8 x 8 tile), so the lanes of a wave
 // walk the same stretch of neighbouring rays and their gathers stay coherent.
-// Partial sums meet in LDS.  blockIdx.y = view offset; blockIdx.x indexes the
-// geometry's dispatch order (per-XCD row bands, centre-out columns).
+// Partial sums meet in LDS.  blockIdx.y = item of the launch (a scan and one of
+// its views); blockIdx.x indexes that geometry's dispatch order (per-XCD row
+// bands, centre-out columns); workgroups past the item's tile count exit.
 template <int VT, int PT, bool SART>
-__global__ __launch_bounds__(256) void fp_kernel(GeomDev g, const void *__restrict__ vol, void *__restrict__ proj,
-                                                 int view_begin, int nsplit, const void *__restrict__ pw, int pwt,
-                                                 float *__restrict__ rho) {
+__global__ __launch_bounds__(256) void fp_kernel(const FpLaunch L) {
+    const FpItem &item = L.item[blockIdx.y];
+    if ((int)blockIdx.x >= item.nwg) return;
+    const GeomDev &g = item.g;
+    const void *__restrict__ vol = item.vol;
+    void *__restrict__ proj = item.proj;
+    const void *__restrict__ pw = item.pw;
+    float *__restrict__ rho = item.rho;
+    const int pwt = item.pwt, nsplit = item.ns;
     extern __shared__ float2 smem[];
     const Tabs T = stage_tables(g, smem);
     float *part = (float *)(smem + table_floats2(g));
     __syncthreads();
-    const int k = view_begin + blockIdx.y;
+    const int k = item.view;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int groups = 4 / nsplit;           // 8x8 pixel groups per workgroup
     const int piece = wave % nsplit, grp = wave / nsplit;
@@ -901,9 +945,17 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Vi
 // MODE 0: vol = (accumulate ? vol : 0) + c.  MODE 1 (SART, one view):
 // vol += lam * wv * c / n where n > 0.
 template <int VT, int PT, int MODE>
-__global__ __launch_bounds__(256) void bp_kernel(GeomDev g, const void *__restrict__ y, int view_begin, int view_end,
-                                                 void *__restrict__ vol, int accumulate, const float *__restrict__ rho,
-                                                 const void *__restrict__ vw, int vwt, float lam, int nonneg) {
+__global__ __launch_bounds__(256) void bp_kernel(const BpLaunch L) {
+    const BpItem &item = L.item[blockIdx.y];
+    if ((int)blockIdx.x >= item.nwg) return;
+    const GeomDev &g = item.g;
+    const void *__restrict__ y = item.y;
+    const float *__restrict__ rho = (const float *)item.y;
+    void *__restrict__ vol = item.vol;
+    const void *__restrict__ vw = item.vw;
+    const int view_begin = item.view_begin, view_end = item.view_end;
+    const int accumulate = item.accumulate, vwt = item.vwt, nonneg = item.nonneg;
+    const float lam = item.lam;
     extern __shared__ float2 smem[];
     const Tabs T = stage_tables(g, smem, false);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -1010,8 +1062,9 @@ static size_t bp_lds_bytes(const GeomDev &g, bool sart) {
            4 * sizeof(float) * (size_t)(g.bh * (g.bt * (g.br + 1) + 1) + 1) * (sart ? 2 : 1);
 }
 
-// Rays per launch below which each ray is split over neighbouring lanes so one
-// view still fills the GPU.
+// Rays per item below which each ray is split over neighbouring lanes so one
+// view still fills the GPU.  Chosen per item, so an item's result does not
+// depend on what else shares its launch.
 static int fp_split(const GeomDev &g, int nv) {
     const long rays = (long)g.rows * g.cols * nv;
     if (rays >= (4L << 20)) return 1;
@@ -1019,75 +1072,142 @@ static int fp_split(const GeomDev &g, int nv) {
     return 4;
 }
 
-template <int VT, int PT>
-static void launch_fp_t(const cyl_geom *G, const void *vol, void *proj, int vb, int nv, bool sart, const void *pw,
-                        int pwt, float *rho, hipStream_t st) {
+static FpItem fp_item(const cyl_geom *G, const void *vol, void *proj, int view, int ns, const void *pw, int pwt,
+                      float *rho) {
     const GeomDev &g = G->dev;
-    const int ns = fp_split(g, nv);
     const int tw = 8 * (4 / ns);
-    dim3 grid(((g.cols + tw - 1) / tw) * ((g.rows + 7) / 8), nv);
-    const size_t lds = table_bytes(g) + 256 * sizeof(float);
+    FpItem it;
+    it.g = G->dev;
+    it.vol = vol;
+    it.proj = proj;
+    it.pw = pw;
+    it.rho = rho;
+    it.view = view;
+    it.ns = ns;
+    it.nwg = ((g.cols + tw - 1) / tw) * ((g.rows + 7) / 8);
+    it.pwt = pwt;
+    return it;
+}
+
+static BpItem bp_item(const cyl_geom *G, const void *y, int vb, int ve, void *vol, int accumulate, const void *vw,
+                      int vwt, float lam, int nonneg) {
+    const GeomDev &g = G->dev;
+    BpItem it;
+    it.g = G->dev;
+    it.y = y;
+    it.vol = vol;
+    it.vw = vw;
+    it.view_begin = vb;
+    it.view_end = ve;
+    it.nwg = g.nbr * g.nbt * ((g.nbh + 3) / 4);
+    it.accumulate = accumulate;
+    it.vwt = vwt;
+    it.nonneg = nonneg;
+    it.lam = lam;
+    return it;
+}
+
+// Launch sizes of a batch: the widest item sets grid.x, the largest tables set
+// the LDS.
+struct LaunchShape {
+    int maxwg = 0;
+    size_t lds = 0;
+};
+
+template <int VT, int PT>
+static void launch_fp_t(const FpLaunch &L, const LaunchShape &sh, bool sart, hipStream_t st) {
+    dim3 grid(sh.maxwg, L.n);
     if (sart)
-        hipLaunchKernelGGL((fp_kernel<VT, PT, true>), grid, dim3(256), lds, st, g, vol, proj, vb, ns, pw, pwt, rho);
+        hipLaunchKernelGGL((fp_kernel<VT, PT, true>), grid, dim3(256), sh.lds, st, L);
     else
-        hipLaunchKernelGGL((fp_kernel<VT, PT, false>), grid, dim3(256), lds, st, g, vol, proj, vb, ns, pw, pwt, rho);
+        hipLaunchKernelGGL((fp_kernel<VT, PT, false>), grid, dim3(256), sh.lds, st, L);
 }
 
 template <int VT>
-static void launch_fp_v(const cyl_geom *G, const void *vol, void *proj, int pt, int vb, int nv, bool sart,
-                        const void *pw, int pwt, float *rho, hipStream_t st) {
+static void launch_fp_v(const FpLaunch &L, const LaunchShape &sh, int pt, bool sart, hipStream_t st) {
     switch (pt) {
-        case CYL_F32: launch_fp_t<VT, CYL_F32>(G, vol, proj, vb, nv, sart, pw, pwt, rho, st); break;
-        case CYL_F16: launch_fp_t<VT, CYL_F16>(G, vol, proj, vb, nv, sart, pw, pwt, rho, st); break;
-        default: launch_fp_t<VT, CYL_BF16>(G, vol, proj, vb, nv, sart, pw, pwt, rho, st); break;
+        case CYL_F32: launch_fp_t<VT, CYL_F32>(L, sh, sart, st); break;
+        case CYL_F16: launch_fp_t<VT, CYL_F16>(L, sh, sart, st); break;
+        default: launch_fp_t<VT, CYL_BF16>(L, sh, sart, st); break;
     }
 }
 
+// Launches a filled FpLaunch (1 <= L.n <= kMaxBatch); geoms[i] is item i's geometry.
+static void launch_fp_batch(const FpLaunch &L, const cyl_geom *const *geoms, int vt, int pt, bool sart,
+                            hipStream_t st) {
+    LaunchShape sh;
+    for (int i = 0; i < L.n; ++i) {
+        sh.maxwg = std::max(sh.maxwg, L.item[i].nwg);
+        sh.lds = std::max(sh.lds, table_bytes(geoms[i]->dev) + 256 * sizeof(float));
+    }
+    switch (vt) {
+        case CYL_F32: launch_fp_v<CYL_F32>(L, sh, pt, sart, st); break;
+        case CYL_F16: launch_fp_v<CYL_F16>(L, sh, pt, sart, st); break;
+        default: launch_fp_v<CYL_BF16>(L, sh, pt, sart, st); break;
+    }
+}
+
+// Plain or SART FP of views [vb, vb + nv) of one scan, kMaxBatch views per launch.
 static void launch_fp(const cyl_geom *G, const void *vol, int vt, void *proj, int pt, int vb, int nv, bool sart,
                       const void *pw, int pwt, float *rho, hipStream_t st) {
-    switch (vt) {
-        case CYL_F32: launch_fp_v<CYL_F32>(G, vol, proj, pt, vb, nv, sart, pw, pwt, rho, st); break;
-        case CYL_F16: launch_fp_v<CYL_F16>(G, vol, proj, pt, vb, nv, sart, pw, pwt, rho, st); break;
-        default: launch_fp_v<CYL_BF16>(G, vol, proj, pt, vb, nv, sart, pw, pwt, rho, st); break;
+    const int ns = fp_split(G->dev, nv);
+    const cyl_geom *geoms[kMaxBatch];
+    for (int v0 = 0; v0 < nv; v0 += kMaxBatch) {
+        FpLaunch L;
+        L.n = std::min(kMaxBatch, nv - v0);
+        for (int i = 0; i < L.n; ++i) {
+            L.item[i] = fp_item(G, vol, proj, vb + v0 + i, ns, pw, pwt, rho);
+            geoms[i] = G;
+        }
+        launch_fp_batch(L, geoms, vt, pt, sart, st);
     }
 }
 
 template <int VT, int PT>
-static void launch_bp_t(const cyl_geom *G, const void *y, int vb, int ve, void *vol, int accumulate, bool sart,
-                        const float *rho, const void *vw, int vwt, float lam, int nonneg, hipStream_t st) {
-    const GeomDev &g = G->dev;
-    dim3 grid(g.nbr * g.nbt * ((g.nbh + 3) / 4));
-    const size_t lds = bp_lds_bytes(g, sart);
+static void launch_bp_t(const BpLaunch &L, const LaunchShape &sh, bool sart, hipStream_t st) {
+    dim3 grid(sh.maxwg, L.n);
     if (sart)
-        hipLaunchKernelGGL((bp_kernel<VT, PT, 1>), grid, dim3(256), lds, st, g, y, vb, ve, vol, accumulate, rho, vw,
-                           vwt, lam, nonneg);
+        hipLaunchKernelGGL((bp_kernel<VT, PT, 1>), grid, dim3(256), sh.lds, st, L);
     else
-        hipLaunchKernelGGL((bp_kernel<VT, PT, 0>), grid, dim3(256), lds, st, g, y, vb, ve, vol, accumulate, rho, vw,
-                           vwt, lam, nonneg);
+        hipLaunchKernelGGL((bp_kernel<VT, PT, 0>), grid, dim3(256), sh.lds, st, L);
 }
 
 template <int VT>
-static void launch_bp_v(const cyl_geom *G, const void *y, int pt, int vb, int ve, void *vol, int accumulate,
-                        bool sart, const float *rho, const void *vw, int vwt, float lam, int nonneg,
-                        hipStream_t st) {
+static void launch_bp_v(const BpLaunch &L, const LaunchShape &sh, int pt, bool sart, hipStream_t st) {
     if (sart) {  // the SART update reads FP32 residuals, not the projections
-        launch_bp_t<VT, CYL_F32>(G, y, vb, ve, vol, accumulate, sart, rho, vw, vwt, lam, nonneg, st);
+        launch_bp_t<VT, CYL_F32>(L, sh, sart, st);
         return;
     }
     switch (pt) {
-        case CYL_F32: launch_bp_t<VT, CYL_F32>(G, y, vb, ve, vol, accumulate, sart, rho, vw, vwt, lam, nonneg, st); break;
-        case CYL_F16: launch_bp_t<VT, CYL_F16>(G, y, vb, ve, vol, accumulate, sart, rho, vw, vwt, lam, nonneg, st); break;
-        default: launch_bp_t<VT, CYL_BF16>(G, y, vb, ve, vol, accumulate, sart, rho, vw, vwt, lam, nonneg, st); break;
+        case CYL_F32: launch_bp_t<VT, CYL_F32>(L, sh, sart, st); break;
+        case CYL_F16: launch_bp_t<VT, CYL_F16>(L, sh, sart, st); break;
+        default: launch_bp_t<VT, CYL_BF16>(L, sh, sart, st); break;
     }
 }
 
+static void launch_bp_batch(const BpLaunch &L, const cyl_geom *const *geoms, int vt, int pt, bool sart,
+                            hipStream_t st) {
+    LaunchShape sh;
+    for (int i = 0; i < L.n; ++i) {
+        sh.maxwg = std::max(sh.maxwg, L.item[i].nwg);
+        sh.lds = std::max(sh.lds, bp_lds_bytes(geoms[i]->dev, sart));
+    }
+    switch (vt) {
+        case CYL_F32: launch_bp_v<CYL_F32>(L, sh, pt, sart, st); break;
+        case CYL_F16: launch_bp_v<CYL_F16>(L, sh, pt, sart, st); break;
+        default: launch_bp_v<CYL_BF16>(L, sh, pt, sart, st); break;
+    }
+}
+
+// Plain BP of views [vb, ve) (one item: the views accumulate in LDS) or the
+// SART update of one view.
 static void launch_bp(const cyl_geom *G, const void *y, int pt, int vb, int ve, void *vol, int vt, int accumulate,
                       bool sart, const float *rho, const void *vw, int vwt, float lam, int nonneg, hipStream_t st) {
-    switch (vt) {
-        case CYL_F32: launch_bp_v<CYL_F32>(G, y, pt, vb, ve, vol, accumulate, sart, rho, vw, vwt, lam, nonneg, st); break;
-        case CYL_F16: launch_bp_v<CYL_F16>(G, y, pt, vb, ve, vol, accumulate, sart, rho, vw, vwt, lam, nonneg, st); break;
-        default: launch_bp_v<CYL_BF16>(G, y, pt, vb, ve, vol, accumulate, sart, rho, vw, vwt, lam, nonneg, st); break;
-    }
+    BpLaunch L;
+    L.n = 1;
+    L.item[0] = bp_item(G, sart ? (const void *)rho : y, vb, ve, vol, accumulate, vw, vwt, lam, nonneg);
+    const cyl_geom *geoms[1] = {G};
+    launch_bp_batch(L, geoms, vt, pt, sart, st);
 }
 
 // Makes the geometry's device current for the duration of a call.
@@ -1300,4 +1420,78 @@ extern "C" int cyl_sart_update(const cyl_geom *G, int32_t view, double lambda, i
     launch_bp(G, nullptr, CYL_F32, view, view + 1, vol, vt, 0, true, (const float *)workspace, vw, vwt,
               (float)lambda, nonneg, (hipStream_t)hip_stream);
     return launch_check("cyl_sart_update");
+}
+
+extern "C" int cyl_sart_batch_step(int32_t n, const cyl_sart_batch_item *items, cyl_dtype pt, cyl_dtype pwt,
+                                   cyl_dtype vwt, cyl_dtype vt, void *hip_stream) {
+    if (n < 0 || (n > 0 && !items)) {
+        set_error("cyl_sart_batch_step: need n >= 0 and an items array");
+        return CYL_EINVAL;
+    }
+    if (n == 0) return CYL_OK;
+    int rc;
+    if ((rc = check_dtype(vt, "cyl_sart_batch_step volume")) ||
+        (rc = check_dtype(pt, "cyl_sart_batch_step projections")))
+        return rc;
+    bool any_pw = false, any_vw = false;
+    for (int i = 0; i < n; ++i) {
+        const cyl_sart_batch_item &it = items[i];
+        if (!it.geom || !it.proj || !it.vol) {
+            set_error("cyl_sart_batch_step: item %d has a NULL geometry, projection or volume", i);
+            return CYL_EINVAL;
+        }
+        if (it.geom->device != items[0].geom->device) {
+            set_error("cyl_sart_batch_step: item %d is on device %d, item 0 on %d", i, it.geom->device,
+                      items[0].geom->device);
+            return CYL_EINVAL;
+        }
+        if (it.view < 0 || it.view >= it.geom->n_views) {
+            set_error("cyl_sart_batch_step: item %d view %d outside [0, %d)", i, it.view, it.geom->n_views);
+            return CYL_EINVAL;
+        }
+        const size_t need = cyl_sart_workspace_bytes(it.geom, nullptr);
+        if (!it.workspace || it.workspace_bytes < need) {
+            set_error("cyl_sart_batch_step: item %d workspace of %zu bytes is smaller than the %zu needed", i,
+                      it.workspace_bytes, need);
+            return CYL_EINVAL;
+        }
+        if (!std::isfinite(it.lambda)) {
+            set_error("cyl_sart_batch_step: item %d lambda must be finite", i);
+            return CYL_EINVAL;
+        }
+        any_pw |= it.proj_weights != nullptr;
+        any_vw |= it.vox_weights != nullptr;
+    }
+    if (any_pw && (rc = check_dtype(pwt, "cyl_sart_batch_step projection weights"))) return rc;
+    if (any_vw && (rc = check_dtype(vwt, "cyl_sart_batch_step voxel weights"))) return rc;
+    DeviceGuard dg(items[0].geom->device);
+    if (!dg.ok) {
+        set_error("cyl_sart_batch_step: cannot select device %d", items[0].geom->device);
+        return CYL_EDEVICE;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    const cyl_geom *geoms[kMaxBatch];
+    for (int i0 = 0; i0 < n; i0 += kMaxBatch) {
+        FpLaunch L;
+        L.n = std::min(kMaxBatch, n - i0);
+        for (int i = 0; i < L.n; ++i) {
+            const cyl_sart_batch_item &it = items[i0 + i];
+            L.item[i] = fp_item(it.geom, it.vol, const_cast<void *>(it.proj), it.view, fp_split(it.geom->dev, 1),
+                                it.proj_weights, pwt, (float *)it.workspace);
+            geoms[i] = it.geom;
+        }
+        launch_fp_batch(L, geoms, vt, pt, true, st);
+    }
+    for (int i0 = 0; i0 < n; i0 += kMaxBatch) {
+        BpLaunch L;
+        L.n = std::min(kMaxBatch, n - i0);
+        for (int i = 0; i < L.n; ++i) {
+            const cyl_sart_batch_item &it = items[i0 + i];
+            L.item[i] = bp_item(it.geom, it.workspace, it.view, it.view + 1, it.vol, 0, it.vox_weights, vwt,
+                                (float)it.lambda, it.nonneg);
+            geoms[i] = it.geom;
+        }
+        launch_bp_batch(L, geoms, vt, CYL_F32, true, st);
+    }
+    return launch_check("cyl_sart_batch_step");
 }

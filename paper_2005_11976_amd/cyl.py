@@ -19,7 +19,7 @@ CYL_OK, CYL_EINVAL, CYL_ENOMEM, CYL_EDEVICE, CYL_EUNSUPPORTED = 0, -1, -2, -3, -
 
 EXPORTS = ["cyl_geom_create", "cyl_geom_destroy", "cyl_fp", "cyl_bp", "cyl_row_sums",
            "cyl_sart_workspace_bytes", "cyl_sart_run", "cyl_sart_residual", "cyl_sart_update",
-           "cyl_last_error", "cyl_version"]
+           "cyl_sart_batch_step", "cyl_last_error", "cyl_version"]
 
 
 class CylError(RuntimeError):
@@ -49,6 +49,13 @@ class cyl_sart_params(C.Structure):
                 ("start_view", C.c_int32)]
 
 
+class cyl_sart_batch_item(C.Structure):
+    _fields_ = [("geom", C.c_void_p), ("view", C.c_int32), ("proj", C.c_void_p),
+                ("proj_weights", C.c_void_p), ("vox_weights", C.c_void_p), ("vol", C.c_void_p),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t), ("lam", C.c_double),
+                ("nonneg", C.c_int32)]
+
+
 _lib = None
 
 
@@ -76,6 +83,9 @@ def declare(lib):
     lib.cyl_sart_update.argtypes = [vp, i32, C.c_double, i32, vp, C.c_int, vp, C.c_int, vp,
                                     C.c_size_t, vp]
     lib.cyl_sart_update.restype = C.c_int
+    lib.cyl_sart_batch_step.argtypes = [i32, P(cyl_sart_batch_item), C.c_int, C.c_int, C.c_int,
+                                         C.c_int, vp]
+    lib.cyl_sart_batch_step.restype = C.c_int
     lib.cyl_last_error.argtypes = []
     lib.cyl_last_error.restype = C.c_char_p
     lib.cyl_version.argtypes = []
@@ -269,3 +279,54 @@ class Geometry:
             _dtype_code(vox_weights) if vox_weights is not None else CYL_F32,
             C.c_void_p(vol.data_ptr()), _dtype_code(vol), C.c_void_p(workspace.data_ptr()),
             workspace.numel() * workspace.element_size(), _stream_ptr(stream)), self._L)
+
+
+class BatchEntry:
+    """One scan's part of a batched SART sub-iteration (see sart_batch_step)."""
+
+    def __init__(self, geom, view, proj, vol, workspace, proj_weights=None, vox_weights=None,
+                 lam=0.5, nonneg=False):
+        self.geom, self.view, self.proj, self.vol = geom, int(view), proj, vol
+        self.workspace, self.proj_weights, self.vox_weights = workspace, proj_weights, vox_weights
+        self.lam, self.nonneg = float(lam), bool(nonneg)
+
+
+def sart_batch_step(entries, stream=None, _lib=None):
+    """cyl_sart_batch_step: one SART sub-iteration (FP + residual, then BP +
+    update) for every entry, in two launches for up to 16 entries.  Storage
+    types must agree across entries."""
+    L = _lib or lib()
+    n = len(entries)
+    if n == 0:
+        return
+    arr = (cyl_sart_batch_item * n)()
+    e0 = entries[0]
+    for i, e in enumerate(entries):
+        e.geom._proj(e.proj)
+        e.geom._vol(e.vol)
+        for t, ref, what in ((e.proj, e0.proj, "projections"), (e.vol, e0.vol, "volumes")):
+            if t.dtype != ref.dtype:
+                raise TypeError("batch entries must share the %s dtype" % what)
+        if e.proj_weights is not None:
+            e.geom._proj(e.proj_weights)
+        if e.vox_weights is not None:
+            e.geom._vol(e.vox_weights)
+        a = arr[i]
+        a.geom = e.geom.handle.value
+        a.view = e.view
+        a.proj = e.proj.data_ptr()
+        a.proj_weights = e.proj_weights.data_ptr() if e.proj_weights is not None else None
+        a.vox_weights = e.vox_weights.data_ptr() if e.vox_weights is not None else None
+        a.vol = e.vol.data_ptr()
+        a.workspace = e.workspace.data_ptr()
+        a.workspace_bytes = e.workspace.numel() * e.workspace.element_size()
+        a.lam = e.lam
+        a.nonneg = int(e.nonneg)
+    pws = [e.proj_weights for e in entries if e.proj_weights is not None]
+    vws = [e.vox_weights for e in entries if e.vox_weights is not None]
+    if len({t.dtype for t in pws}) > 1 or len({t.dtype for t in vws}) > 1:
+        raise TypeError("batch entries must share the weight dtypes")
+    pwt = _dtype_code(pws[0]) if pws else CYL_F32
+    vwt = _dtype_code(vws[0]) if vws else CYL_F32
+    _check(L.cyl_sart_batch_step(n, arr, _dtype_code(e0.proj), pwt, vwt, _dtype_code(e0.vol),
+                                 _stream_ptr(stream)), L)
