@@ -57,7 +57,44 @@ def parse():
                     help="views in the per-kernel HIP-event timing pass")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--serve-requests", type=int, default=16,
+                    help="requests in the serving measurement (0 = skip it)")
+    ap.add_argument("--serve-iters", type=int, default=15)
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate, scans/s")
     return ap.parse_args()
+
+
+def serving(args):
+    """Continuous batching (FP16 storage) against the plain per-scan FP32 loop
+    on the same request stream: classes A/B/C, seeded poses, Poisson arrivals."""
+    import torch
+    from paper_2005_11976_amd import inputs as I, serve
+    classes = I.serving_classes()
+    reqs = I.serving_requests(args.serve_requests, args.serve_rate)
+    used = sorted({q.cls for q in reqs})
+    log("serving:", len(reqs), "requests, classes", [classes[c].name for c in used])
+    phantoms = [I.industrial_phantom(c.grid, c.phantom_seed) for c in classes]
+    res16 = [serve.Resident(c, torch.float16, 0, ph) for c, ph in zip(classes, phantoms)]
+    res32 = [serve.Resident(c, torch.float32, 0, ph) for c, ph in zip(classes, phantoms)]
+    data = serve.make_request_data(res32, reqs, phantoms=phantoms)  # measured FP32 projections
+    del phantoms
+    torch.cuda.synchronize()
+    srv = serve.Server(res16, n_iter=args.serve_iters, max_active=16, hbm_budget=64 << 30)
+    log("serving: batched run")
+    recs, vols = srv.run(reqs, data)
+    log("serving: per-scan FP32 run")
+    frecs, fvols = serve.run_fifo(res32, reqs, data, n_iter=args.serve_iters)
+    errs = [float((vols[q.rid].float() - fvols[q.rid]).norm() / fvols[q.rid].norm()) for q in reqs]
+    b, f = serve.latency_summary(recs), serve.latency_summary(frecs)
+    log("serving: batched p50 %.2f s p99 %.2f s %.3f scans/s; fifo p50 %.2f s p99 %.2f s %.3f scans/s"
+        % (b["p50_s"], b["p99_s"], b["scans_per_s"], f["p50_s"], f["p99_s"], f["scans_per_s"]))
+    return {"requests": len(reqs), "rate_per_s": args.serve_rate, "iterations": args.serve_iters,
+            "classes": "".join(classes[c].name for c in used),
+            "dtype": "f16 storage (prior + difference form), f32 arithmetic",
+            "hbm_budget_gb": 64, "slots": 16, "fill_rays": srv.fill_rays, "batched": b, "per_scan_fp32": f,
+            "throughput_ratio": b["scans_per_s"] / f["scans_per_s"],
+            "p99_ratio": b["p99_s"] / f["p99_s"],
+            "rel_err_vs_per_scan_fp32": {"max": max(errs), "mean": float(np.mean(errs))}}
 
 
 def cpu_baseline(scan, truth, prior, weights, p, nthreads):
@@ -187,6 +224,8 @@ def main():
         log("copy calibration: 1 GiB read + 1 GiB written")
         del src, dst
 
+    serving_out = serving(args) if args.serve_requests > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         nthreads = max(1, min(16, len(os.sched_getaffinity(0))))
@@ -218,6 +257,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": dom_bytes},
         "cpu_baseline": cpu,
+        "serving": serving_out,
         "rel_err_vs_truth": rel_truth,
     }
     print(json.dumps(out), flush=True)

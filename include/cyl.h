@@ -177,6 +177,25 @@ int cyl_sart_update(const cyl_geom *geom, int32_t view, double lambda, int32_t n
                     const void *vox_weights, cyl_dtype vox_weights_type, void *vol, cyl_dtype vol_type,
                     const void *workspace, size_t workspace_bytes, void *hip_stream);
 
+/* out[k] = base[k] - A_k vol for views k in [view_begin, view_end): given
+ * projections minus the forward projection of a volume (Eq. 6), formed in FP32
+ * and rounded once into out_type.  With vol = the prior it gives the data of
+ * SART run on the difference from the prior (Sec. 2.2 starts from a prior):
+ * SART from mu(0) on p equals mu(0) + SART from 0 on p - A mu(0), and the
+ * difference and its projections are small, so FP16/BF16 storage holds them
+ * with little error.  Layouts as cyl_fp; base and out may be the same buffer.
+ * Errors as cyl_fp. */
+int cyl_fp_diff(const cyl_geom *geom, const void *vol, cyl_dtype vol_type, const void *base,
+                cyl_dtype base_type, void *out, cyl_dtype out_type, int32_t view_begin,
+                int32_t view_end, void *hip_stream);
+
+/* out = a + b over n values of device memory on HIP device `device`
+ * (storage types a_type, b_type, out_type; FP32 arithmetic, rounded to
+ * nearest-even on store); out may alias a or b.  Used to form prior + difference
+ * volumes.  CYL_EINVAL for n < 0 or a NULL array. */
+int cyl_add(int64_t n, const void *a, cyl_dtype a_type, const void *b, cyl_dtype b_type, void *out,
+            cyl_dtype out_type, int32_t device, void *hip_stream);
+
 /* One SART sub-iteration (Eq. 7 with the ordered subset = one projection,
  * Sec. 2.2) for each of n independent scans, in two launches: the forward
  * projections with residuals of all items, then their back-projections with
@@ -211,6 +230,43 @@ typedef struct {
 int cyl_sart_batch_step(int32_t n, const cyl_sart_batch_item *items, cyl_dtype proj_type,
                         cyl_dtype proj_weights_type, cyl_dtype vox_weights_type, cyl_dtype vol_type,
                         void *hip_stream);
+
+/* ---- pose estimation from projections (Sec. 2.1) ---------------------- */
+
+/* Corner pixels of the segmented object in each projection (axis tracking):
+ * pixels whose value exceeds `threshold` (rounded to FP32), dilated by a square
+ * of half-width `dilate`; with u the column and v the row index, the corners
+ * are top-left = min u+v, top-right = max u-v (ties: smallest v), bottom-left =
+ * min u-v, bottom-right = max u+v (ties: largest v).  The pairwise centres of
+ * the two top and the two bottom corners are two points of the projected
+ * symmetry axis.
+ *   proj     device, [n_views][rows][cols] of proj_type
+ *   corners  device int32, [n_views][9]: TL.u TL.v TR.u TR.v BL.u BL.v BR.u BR.v
+ *            and the number of pixels above the threshold; the corners are -1
+ *            for a view with none.
+ * Exact integer results (independent of the reduction order).  CYL_EINVAL for
+ * bad sizes or NULL buffers; asynchronous on hip_stream of device `device`. */
+int cyl_axis_corners(int32_t n_views, int32_t rows, int32_t cols, const void *proj, cyl_dtype proj_type,
+                     double threshold, int32_t dilate, int32_t *corners, int32_t device, void *hip_stream);
+
+/* Point tracking, Eq. 3-4: the stage-frame point X minimising
+ * sum_k |uv_k - V_k(X)|^2 over the views k with valid[k] != 0 (valid may be
+ * NULL = all), V_k the cone-beam projection of view k to detector coordinates
+ * (u = column, v = row, pixel centres at integers).  Levenberg-Marquardt with
+ * analytic derivatives from the least-squares intersection of the views'
+ * rays.  Host call on host arrays: uv [n_views][2]; writes xyz[3] and, if rms
+ * is not NULL, the root-mean-square residual in pixels.  CYL_EINVAL for fewer
+ * than two valid views, non-finite points or a degenerate detector. */
+int cyl_track_point(const cyl_traj *traj, const double *uv, const uint8_t *valid, double *xyz, double *rms);
+
+/* Pose (Eq. 1, X' = R X + T with R = Rz(alpha) Rx(beta) Rz(gamma)) from two
+ * stage-frame points of the object's symmetry axis at object heights
+ * h_top > h_bottom, and the internal rotation angle alpha about that axis:
+ * beta and gamma follow from the axis direction R^T z, and the object origin
+ * (the axis point at height 0) from the points' midpoint.  Host call.
+ * CYL_EINVAL for coincident points, h_top <= h_bottom or non-finite values. */
+int cyl_pose_from_axis(const double *top, const double *bottom, double h_top, double h_bottom, double alpha,
+                       cyl_pose *out);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *cyl_last_error(void);

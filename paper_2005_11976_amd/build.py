@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcyl.so")
-SOURCES = ["cyl_host.cpp", "cyl_kernels.hip"]
+SOURCES = ["cyl_host.cpp", "cyl_pose.cpp", "cyl_kernels.hip", "cyl_axis.hip"]
 ARCH = "gfx950"
 
 
@@ -27,7 +27,7 @@ def hipcc():
 def flags():
     return [
         "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
-        # packed FP32 instructions stay off (see the build notes in the design doc)
+        # packed FP32 instructions stay off: some of their forms have produced wrong results
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I" + os.path.join(ROOT, "include"),
         "-Wall", "-Wno-unused-function", "-Wno-unused-result",

@@ -1,0 +1,131 @@
+// Projected-axis points for pose estimation (Sec. 2.1, axis tracking).
+//
+// Per view: the object is segmented by a threshold on the line integrals and a
+// square dilation of half-width k, and the four corner pixels of the segment
+// are found.  With u the column and v the row, top-left minimises u + v,
+// top-right maximises u - v (ties: smallest v), bottom-left minimises u - v,
+// bottom-right maximises u + v (ties: largest v).  The dilation is not formed:
+// over a dilated set, each of these keys is extreme at a window corner of a
+// seed pixel (the window clipped to the detector), so every seed pixel
+// contributes one candidate per corner, and the four corners are four
+// integer minimum reductions of (key, tie) packed into 64 bits: exact and
+// independent of the reduction order.
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+
+#include "cyl_internal.h"
+
+namespace cyl {
+
+namespace {
+
+__device__ __forceinline__ float load_any(const void *p, int dt, size_t i) {
+    if (dt == CYL_F32) return ((const float *)p)[i];
+    if (dt == CYL_F16) return __half2float(((const __half *)p)[i]);
+    return __uint_as_float((uint32_t)((const uint16_t *)p)[i] << 16);
+}
+
+__device__ __forceinline__ uint64_t pack(uint32_t key, uint32_t tie) { return ((uint64_t)key << 32) | tie; }
+
+__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
+
+// One workgroup per view.  out[view] = {TL.u, TL.v, TR.u, TR.v, BL.u, BL.v,
+// BR.u, BR.v, seed count (saturated)}; corners are -1 for an empty segment.
+__global__ __launch_bounds__(256) void axis_corner_kernel(const void *__restrict__ proj, int pt, int rows, int cols,
+                                                          float threshold, int k, int32_t *__restrict__ out) {
+    const int view = blockIdx.x;
+    const size_t npix = (size_t)rows * cols;
+    const size_t base = (size_t)view * npix;
+    const uint32_t W = (uint32_t)cols, H = (uint32_t)rows;
+    uint64_t m0 = ~0ull, m1 = ~0ull, m2 = ~0ull, m3 = ~0ull;
+    uint32_t count = 0;
+    for (size_t j = threadIdx.x; j < npix; j += blockDim.x) {
+        if (!(load_any(proj, pt, base + j) > threshold)) continue;
+        ++count;
+        const int v = (int)(j / cols), u = (int)(j % cols);
+        const uint32_t ulo = (uint32_t)(u - k < 0 ? 0 : u - k), uhi = (uint32_t)(u + k >= cols ? cols - 1 : u + k);
+        const uint32_t vlo = (uint32_t)(v - k < 0 ? 0 : v - k), vhi = (uint32_t)(v + k >= rows ? rows - 1 : v + k);
+        m0 = umin64(m0, pack(ulo + vlo, vlo));                   // min u+v, smallest v
+        m1 = umin64(m1, pack(W + vlo - uhi, vlo));               // max u-v, smallest v
+        m2 = umin64(m2, pack(H + ulo - vhi, H - 1 - vhi));       // min u-v, largest v
+        m3 = umin64(m3, pack(W + H - uhi - vhi, H - 1 - vhi));   // max u+v, largest v
+    }
+    __shared__ uint64_t red[4][256];
+    __shared__ uint32_t cnt[256];
+    red[0][threadIdx.x] = m0;
+    red[1][threadIdx.x] = m1;
+    red[2][threadIdx.x] = m2;
+    red[3][threadIdx.x] = m3;
+    cnt[threadIdx.x] = count;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = umin64(red[c][threadIdx.x], red[c][threadIdx.x + s]);
+            const uint32_t a = cnt[threadIdx.x], b = cnt[threadIdx.x + s];
+            cnt[threadIdx.x] = a + b < a ? 0xffffffffu : a + b;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    int32_t *o = out + (size_t)view * 9;
+    const uint32_t n = cnt[0];
+    o[8] = (int32_t)(n > 0x7fffffffu ? 0x7fffffffu : n);
+    if (n == 0) {
+        for (int c = 0; c < 8; ++c) o[c] = -1;
+        return;
+    }
+    const uint64_t r0 = red[0][0], r1 = red[1][0], r2 = red[2][0], r3 = red[3][0];
+    uint32_t v;
+    v = (uint32_t)r0;
+    o[0] = (int32_t)((uint32_t)(r0 >> 32) - v);
+    o[1] = (int32_t)v;
+    v = (uint32_t)r1;
+    o[2] = (int32_t)(W + v - (uint32_t)(r1 >> 32));
+    o[3] = (int32_t)v;
+    v = H - 1 - (uint32_t)r2;
+    o[4] = (int32_t)((uint32_t)(r2 >> 32) + v - H);
+    o[5] = (int32_t)v;
+    v = H - 1 - (uint32_t)r3;
+    o[6] = (int32_t)(W + H - (uint32_t)(r3 >> 32) - v);
+    o[7] = (int32_t)v;
+}
+
+}  // namespace
+
+}  // namespace cyl
+
+using namespace cyl;
+
+extern "C" int cyl_axis_corners(int32_t n_views, int32_t rows, int32_t cols, const void *proj, cyl_dtype proj_type,
+                                double threshold, int32_t dilate, int32_t *corners, int32_t device,
+                                void *hip_stream) {
+    if (n_views < 0 || rows < 1 || cols < 1 || dilate < 0 || (n_views > 0 && (!proj || !corners))) {
+        set_error("cyl_axis_corners: need n_views >= 0, rows, cols >= 1, dilate >= 0 and non-NULL buffers");
+        return CYL_EINVAL;
+    }
+    if ((int64_t)rows + cols + 2 * (int64_t)dilate >= (1LL << 30) || (int64_t)rows * cols >= (1LL << 40)) {
+        set_error("cyl_axis_corners: detector of %d x %d too large", rows, cols);
+        return CYL_EINVAL;
+    }
+    int rc;
+    if ((rc = check_dtype(proj_type, "cyl_axis_corners projections"))) return rc;
+    if (n_views == 0) return CYL_OK;
+    int prev = -1;
+    hipGetDevice(&prev);
+    if (prev != device && hipSetDevice(device) != hipSuccess) {
+        set_error("cyl_axis_corners: cannot select device %d", device);
+        return CYL_EDEVICE;
+    }
+    hipLaunchKernelGGL(axis_corner_kernel, dim3(n_views), dim3(256), 0, (hipStream_t)hip_stream, proj,
+                       (int)proj_type, rows, cols, (float)threshold, dilate, corners);
+    hipError_t e = hipGetLastError();
+    if (prev >= 0 && prev != device) hipSetDevice(prev);
+    if (e != hipSuccess) {
+        set_error("cyl_axis_corners: launch failed: %s", hipGetErrorString(e));
+        return CYL_EDEVICE;
+    }
+    return CYL_OK;
+}

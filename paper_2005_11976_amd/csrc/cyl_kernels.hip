@@ -238,6 +238,9 @@ __device__ __forceinline__ EdgeX edge_cross(const GeomDev &g, const ViewDev &V, 
 // Mostly-FP32 ray set-up shared by every kernel.  FP64 is used for the pixel
 // direction, the closest-approach parameter (one FP64 Newton step on an FP32
 // quotient), the closest point and its distance.
+// SUPPORT = false skips the grid-support interval (callers that clip to a
+// smaller region themselves): the interval is then the source-pixel segment.
+template <bool SUPPORT = true>
 __device__ __forceinline__ void ray_geom(const GeomDev &g, const Tabs &T, const ViewDev &V, int u, int v,
                                          RayF &r, double &dxo, double &dyo, double &dzo, double &tco) {
     const double fu = (double)u, fv = (double)v;
@@ -291,20 +294,23 @@ __device__ __forceinline__ void ray_geom(const GeomDev &g, const Tabs &T, const 
     // support interval with the same crossing formulas as the traversal
     bool hit = true;
     if (!(r.flags & RAY_AXIAL)) {
-        const float w = shell_w(T.r[g.n_r], r);
-        if (w < 0.0f) hit = false;
-        s0 = fmaxf(s0, -w);
-        s1 = fminf(s1, w);
+        if (SUPPORT) {
+            const float w = shell_w(T.r[g.n_r], r);
+            if (w < 0.0f) hit = false;
+            s0 = fmaxf(s0, -w);
+            s1 = fminf(s1, w);
+        }
         if (bf == 0.0f && g.n_theta > 1) {
             r.flags |= RAY_THRU;
             r.it_in = sector_of(g, -r.ex, -r.ey);
             r.it_out = sector_of(g, r.ex, r.ey);
         }
-    } else {
+    } else if (SUPPORT) {
         const float2 rt = T.r[g.n_r];
         if (!((rt.x - r.b) + (rt.y - r.blo) > 0.0f)) hit = false;
     }
-    if (fdz != 0.0f) {
+    if (!SUPPORT) {
+    } else if (fdz != 0.0f) {
         const float t1 = plane_s(T.h[0], r), t2 = plane_s(T.h[g.n_h], r);
         s0 = fmaxf(s0, fminf(t1, t2));
         s1 = fminf(s1, fmaxf(t1, t2));
@@ -555,9 +561,9 @@ struct FpItem {
     GeomDev g;
     const void *vol;      // volume (storage type VT)
     void *proj;           // projections: output (plain) or measured data (SART)
-    const void *pw;       // projection weights or null (SART)
+    const void *pw;       // SART: projection weights or null; plain: minuend or null
     float *rho;           // residual image of the view (SART)
-    int view, ns, nwg, pwt;  // view, pieces per ray, workgroups, weight type
+    int view, ns, nwg, pwt;  // view, pieces per ray, workgroups, type of pw
 };
 struct FpLaunch {
     int n;
@@ -665,7 +671,8 @@ __global__ __launch_bounds__(256) void fp_kernel(const FpLaunch L) {
     if (!live) return;
     const size_t j = ((size_t)k * g.rows + v) * g.cols + u;
     if (!SART) {
-        Store<PT>::st(proj, j, acc);
+        // plain projection, or a difference from given projections (pw)
+        Store<PT>::st(proj, j, pw ? ld_any(pw, pwt, j) - acc : acc);
     } else {
         const float L = row_sum_fp64(g, V, r, dx, dy, dz, tc);
         const float pj = Store<PT>::ld(proj, j);
@@ -744,16 +751,18 @@ __device__ __forceinline__ void footprint_point(const GeomDev &g, const Tabs &T,
         const float om = (B.tB - B.tA) * g.dtheta;
         const int nseg = max(1, (int)ceilf(om * (4.0f / 3.14159265f) - 1e-4f));
         const float del = om / nseg;
-        const float rc = rO / cosf(0.5f * del) * (1.0f + 1e-6f);
+        // hardware sine/cosine (~1e-6 absolute): the polygon is inflated by 1e-5
+        // and the pixel box keeps a 0.05-pixel margin, far above that error
+        const float rc = rO / __cosf(0.5f * del) * (1.0f + 1e-5f);
         npoly = nseg + 3;
         if (pi <= nseg) {
             const float ang = thA + pi * del;
-            px = rc * cosf(ang);
-            py = rc * sinf(ang);
+            px = rc * __cosf(ang);
+            py = rc * __sinf(ang);
         } else {
             const float ang = (pi == nseg + 1) ? thA : thA + om;
-            px = rI * cosf(ang);
-            py = rI * sinf(ang);
+            px = rI * __cosf(ang);
+            py = rI * __sinf(ang);
         }
     }
     if (pi >= npoly) return;
@@ -871,7 +880,7 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Vi
                                        int v, float yj, float *acc_c, int *acc_n, float nscale) {
     RayF r;
     double dx, dy, dz, tc;
-    ray_geom(g, T, V, u, v, r, dx, dy, dz, tc);
+    ray_geom<false>(g, T, V, u, v, r, dx, dy, dz, tc);  // the block clip bounds the walk
     if (!(r.flags & RAY_HIT)) return;
     float s0, s1;
     if (!clip_block(g, T, V, r, B, s0, s1)) return;
@@ -1040,6 +1049,16 @@ __global__ __launch_bounds__(256) void bp_kernel(const BpLaunch L) {
             }
         }
     }
+}
+
+// ------------------------------------------------------------ elementwise
+
+// out = a + b over n values (storage types at, bt, ot), FP32 arithmetic.
+template <int OT>
+__global__ __launch_bounds__(256) void add_kernel(size_t n, const void *__restrict__ a, int at,
+                                                  const void *__restrict__ b, int bt, void *__restrict__ out) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        Store<OT>::st(out, i, ld_any(a, at, i) + ld_any(b, bt, i));
 }
 
 // ------------------------------------------------------------ launchers
@@ -1494,4 +1513,51 @@ extern "C" int cyl_sart_batch_step(int32_t n, const cyl_sart_batch_item *items, 
         launch_bp_batch(L, geoms, vt, CYL_F32, true, st);
     }
     return launch_check("cyl_sart_batch_step");
+}
+
+extern "C" int cyl_fp_diff(const cyl_geom *G, const void *vol, cyl_dtype vt, const void *base, cyl_dtype bt,
+                           void *out, cyl_dtype ot, int32_t view_begin, int32_t view_end, void *hip_stream) {
+    if (!G || !vol || !base || !out) {
+        set_error("cyl_fp_diff: NULL argument");
+        return CYL_EINVAL;
+    }
+    int rc;
+    if ((rc = check_dtype(vt, "cyl_fp_diff volume")) || (rc = check_dtype(bt, "cyl_fp_diff base projections")) ||
+        (rc = check_dtype(ot, "cyl_fp_diff output")) || (rc = check_range(G, view_begin, view_end, "cyl_fp_diff")))
+        return rc;
+    if (view_end == view_begin) return CYL_OK;
+    DeviceGuard dg(G->device);
+    if (!dg.ok) {
+        set_error("cyl_fp_diff: cannot select device %d", G->device);
+        return CYL_EDEVICE;
+    }
+    launch_fp(G, vol, vt, out, ot, view_begin, view_end - view_begin, false, base, bt, nullptr,
+              (hipStream_t)hip_stream);
+    return launch_check("cyl_fp_diff");
+}
+
+extern "C" int cyl_add(int64_t n, const void *a, cyl_dtype at, const void *b, cyl_dtype bt, void *out,
+                       cyl_dtype ot, int32_t device, void *hip_stream) {
+    if (n < 0 || (n > 0 && (!a || !b || !out))) {
+        set_error("cyl_add: need n >= 0 and non-NULL arrays");
+        return CYL_EINVAL;
+    }
+    int rc;
+    if ((rc = check_dtype(at, "cyl_add a")) || (rc = check_dtype(bt, "cyl_add b")) ||
+        (rc = check_dtype(ot, "cyl_add out")))
+        return rc;
+    if (n == 0) return CYL_OK;
+    DeviceGuard dg(device);
+    if (!dg.ok) {
+        set_error("cyl_add: cannot select device %d", device);
+        return CYL_EDEVICE;
+    }
+    const size_t blocks = std::min<size_t>(((size_t)n + 255) / 256, 8192);
+    hipStream_t st = (hipStream_t)hip_stream;
+    switch (ot) {
+        case CYL_F32: hipLaunchKernelGGL(add_kernel<CYL_F32>, dim3(blocks), dim3(256), 0, st, (size_t)n, a, at, b, bt, out); break;
+        case CYL_F16: hipLaunchKernelGGL(add_kernel<CYL_F16>, dim3(blocks), dim3(256), 0, st, (size_t)n, a, at, b, bt, out); break;
+        default: hipLaunchKernelGGL(add_kernel<CYL_BF16>, dim3(blocks), dim3(256), 0, st, (size_t)n, a, at, b, bt, out); break;
+    }
+    return launch_check("cyl_add");
 }

@@ -19,7 +19,8 @@ CYL_OK, CYL_EINVAL, CYL_ENOMEM, CYL_EDEVICE, CYL_EUNSUPPORTED = 0, -1, -2, -3, -
 
 EXPORTS = ["cyl_geom_create", "cyl_geom_destroy", "cyl_fp", "cyl_bp", "cyl_row_sums",
            "cyl_sart_workspace_bytes", "cyl_sart_run", "cyl_sart_residual", "cyl_sart_update",
-           "cyl_sart_batch_step", "cyl_last_error", "cyl_version"]
+           "cyl_sart_batch_step", "cyl_fp_diff", "cyl_add", "cyl_axis_corners", "cyl_track_point",
+           "cyl_pose_from_axis", "cyl_last_error", "cyl_version"]
 
 
 class CylError(RuntimeError):
@@ -86,6 +87,17 @@ def declare(lib):
     lib.cyl_sart_batch_step.argtypes = [i32, P(cyl_sart_batch_item), C.c_int, C.c_int, C.c_int,
                                          C.c_int, vp]
     lib.cyl_sart_batch_step.restype = C.c_int
+    lib.cyl_fp_diff.argtypes = [vp, vp, C.c_int, vp, C.c_int, vp, C.c_int, i32, i32, vp]
+    lib.cyl_fp_diff.restype = C.c_int
+    lib.cyl_add.argtypes = [C.c_int64, vp, C.c_int, vp, C.c_int, vp, C.c_int, i32, vp]
+    lib.cyl_add.restype = C.c_int
+    lib.cyl_axis_corners.argtypes = [i32, i32, i32, vp, C.c_int, C.c_double, i32, vp, i32, vp]
+    lib.cyl_axis_corners.restype = C.c_int
+    lib.cyl_track_point.argtypes = [P(cyl_traj), P(C.c_double), P(C.c_uint8), P(C.c_double), P(C.c_double)]
+    lib.cyl_track_point.restype = C.c_int
+    lib.cyl_pose_from_axis.argtypes = [P(C.c_double), P(C.c_double), C.c_double, C.c_double, C.c_double,
+                                       P(cyl_pose)]
+    lib.cyl_pose_from_axis.restype = C.c_int
     lib.cyl_last_error.argtypes = []
     lib.cyl_last_error.restype = C.c_char_p
     lib.cyl_version.argtypes = []
@@ -189,6 +201,22 @@ class Geometry:
                               C.c_void_p(proj.data_ptr()), _dtype_code(proj), view_begin, view_end,
                               _stream_ptr(stream)), self._L)
         return proj
+
+    def fp_diff(self, vol, base, out=None, view_begin=0, view_end=None, out_dtype=None, stream=None):
+        """out = base - A vol (cyl_fp_diff); out defaults to a new tensor of
+        base's dtype (or out_dtype)."""
+        import torch
+        view_end = self.scan.n_views if view_end is None else view_end
+        self._vol(vol)
+        self._proj(base)
+        if out is None:
+            out = torch.empty(self.scan.proj_shape, dtype=out_dtype or base.dtype, device=base.device)
+        self._proj(out)
+        _check(self._L.cyl_fp_diff(self.handle, C.c_void_p(vol.data_ptr()), _dtype_code(vol),
+                                   C.c_void_p(base.data_ptr()), _dtype_code(base),
+                                   C.c_void_p(out.data_ptr()), _dtype_code(out), view_begin, view_end,
+                                   _stream_ptr(stream)), self._L)
+        return out
 
     def bp(self, proj, vol=None, view_begin=0, view_end=None, accumulate=False, out_dtype=None,
            stream=None):
@@ -330,3 +358,76 @@ def sart_batch_step(entries, stream=None, _lib=None):
     vwt = _dtype_code(vws[0]) if vws else CYL_F32
     _check(L.cyl_sart_batch_step(n, arr, _dtype_code(e0.proj), pwt, vwt, _dtype_code(e0.vol),
                                  _stream_ptr(stream)), L)
+
+
+def add(a, b, out=None, stream=None, _lib=None):
+    """out = a + b elementwise on the device (cyl_add), FP32 arithmetic."""
+    import torch
+    L = _lib or lib()
+    if a.numel() != b.numel() or not (a.is_cuda and b.is_cuda and a.is_contiguous() and b.is_contiguous()):
+        raise ValueError("add needs two contiguous CUDA tensors of equal size")
+    if out is None:
+        out = torch.empty_like(a)
+    if out.numel() != a.numel() or not out.is_contiguous():
+        raise ValueError("output size mismatch")
+    _check(L.cyl_add(a.numel(), C.c_void_p(a.data_ptr()), _dtype_code(a), C.c_void_p(b.data_ptr()),
+                     _dtype_code(b), C.c_void_p(out.data_ptr()), _dtype_code(out), a.device.index or 0,
+                     _stream_ptr(stream)), L)
+    return out
+
+
+# -- pose estimation (Sec. 2.1) ------------------------------------------------
+
+def axis_corners(proj, threshold, dilate=1, stream=None, _lib=None):
+    """cyl_axis_corners on a [n_views, rows, cols] CUDA tensor: int32 tensor
+    [n_views, 9] (four corners (u, v) and the segment's seed-pixel count)."""
+    import torch
+    L = _lib or lib()
+    if proj.dim() != 3 or not (proj.is_cuda and proj.is_contiguous()):
+        raise ValueError("projections must be a contiguous CUDA tensor [n_views, rows, cols]")
+    n, rows, cols = proj.shape
+    out = torch.empty((n, 9), dtype=torch.int32, device=proj.device)
+    _check(L.cyl_axis_corners(n, rows, cols, C.c_void_p(proj.data_ptr()), _dtype_code(proj), float(threshold),
+                              int(dilate), C.c_void_p(out.data_ptr()), proj.device.index or 0,
+                              _stream_ptr(stream)), L)
+    return out
+
+
+def axis_points(corners):
+    """Top and bottom axis points (u, v) per view from cyl_axis_corners output
+    (host arrays [n, 2] each, and the mask of views with a segment)."""
+    c = np.asarray(corners, dtype=np.float64)
+    valid = c[:, 8] > 0
+    top = 0.5 * (c[:, 0:2] + c[:, 2:4])
+    bottom = 0.5 * (c[:, 4:6] + c[:, 6:8])
+    return top, bottom, valid
+
+
+def track_point(views, rows, cols, uv, valid=None, _lib=None):
+    """cyl_track_point (host): the stage-frame point best matching detector
+    points uv [n_views, 2] of views (n_views x 12 stage-frame vectors)."""
+    L = _lib or lib()
+    v = np.ascontiguousarray(views, dtype=np.float64)
+    traj = cyl_traj(v.shape[0], rows, cols, v.ctypes.data_as(C.POINTER(C.c_double)))
+    uvc = np.ascontiguousarray(uv, dtype=np.float64)
+    if uvc.shape != (v.shape[0], 2):
+        raise ValueError("uv must be [n_views, 2]")
+    vm = None
+    if valid is not None:
+        vm = np.ascontiguousarray(valid, dtype=np.uint8)
+    xyz = (C.c_double * 3)()
+    rms = C.c_double()
+    _check(L.cyl_track_point(C.byref(traj), uvc.ctypes.data_as(C.POINTER(C.c_double)),
+                             vm.ctypes.data_as(C.POINTER(C.c_uint8)) if vm is not None else None, xyz,
+                             C.byref(rms)), L)
+    return np.array(xyz[:]), rms.value
+
+
+def pose_from_axis(top, bottom, h_top, h_bottom, alpha, _lib=None):
+    """cyl_pose_from_axis (host): (R, T) of Eq. 1."""
+    L = _lib or lib()
+    t = (C.c_double * 3)(*[float(x) for x in top])
+    b = (C.c_double * 3)(*[float(x) for x in bottom])
+    out = cyl_pose()
+    _check(L.cyl_pose_from_axis(t, b, float(h_top), float(h_bottom), float(alpha), C.byref(out)), L)
+    return np.array(out.R[:]).reshape(3, 3), np.array(out.T[:])

@@ -294,3 +294,60 @@ def scaled_single(n_h=32, n_theta=96, n_r=16, n_views=24, det=64, posed_seed=Non
     else:
         R, T, _ = random_pose(posed_seed)
     return Scan(g, views, det, det, R, T)
+
+
+# --------------------------------------------------------------------------
+# the in-line serving stream (three object classes, Poisson arrivals)
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class ScanClass:
+    name: str
+    grid: Grid
+    views: np.ndarray
+    det_rows: int
+    det_cols: int
+    phantom_seed: int
+
+    def scan(self, R, T):
+        return Scan(self.grid, self.views, self.det_rows, self.det_cols, R, T)
+
+
+def serving_classes():
+    """Classes A, B, C of the serving stream (SOD 200 mm, SDD 400 mm):
+    A 128x360x64 (r 12.5, h 25 mm), 60 views of 256x256 at 0.2 mm;
+    B 256x720x128 (r 25, h 50 mm), 90 views of 512x512 at 0.2 mm;
+    C 384x1080x192 (r 37.5, h 75 mm), 120 views of 512 rows x 768 cols at 0.3 mm."""
+    return [
+        ScanClass("A", Grid(128, 360, 64, 0.0, 12.5, -12.5, 12.5), circular_views(60, 200.0, 400.0, 0.2),
+                  256, 256, 1050),
+        ScanClass("B", Grid(256, 720, 128, 0.0, 25.0, -25.0, 25.0), circular_views(90, 200.0, 400.0, 0.2),
+                  512, 512, 1051),
+        ScanClass("C", Grid(384, 1080, 192, 0.0, 37.5, -37.5, 37.5), circular_views(120, 200.0, 400.0, 0.3),
+                  512, 768, 1052),
+    ]
+
+
+@dataclasses.dataclass(frozen=True)
+class Request:
+    rid: int
+    cls: int
+    arrival: float      # seconds from the start of the stream
+    R: np.ndarray
+    T: np.ndarray
+
+
+def serving_requests(n, rate, n_classes=3, seed=6000, classes=None):
+    """n requests with exponential inter-arrival times of mean 1/rate seconds
+    (seed 6000), classes uniform over `classes` (default all n_classes), pose
+    of request r from random_pose(5000 + r) (tilt <= 5 deg, shift <= 2 mm)."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=n)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    pool = list(range(n_classes)) if classes is None else list(classes)
+    kinds = rng.integers(0, len(pool), size=n)
+    out = []
+    for r in range(n):
+        R, T, _ = random_pose(5000 + r)
+        out.append(Request(r, pool[int(kinds[r])], float(arrivals[r]), R, T))
+    return out
