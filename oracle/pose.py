@@ -121,3 +121,57 @@ def pose_from_axis(top, bottom, h_top, h_bottom, alpha):
     R = Rz_a @ Rx_b @ Rz_g
     centre = 0.5 * (top + bottom) - 0.5 * (h_top + h_bottom) * d
     return R, -R @ centre
+
+
+# ---------------------------------------------------------------- azimuthal phase
+
+def side_sums(projs, centres, row_lo, row_hi):
+    """Per view k: (grey-value sum left of the detector position centres[k],
+    sum right of it) over rows [row_lo[k], row_hi[k]] (inclusive, clipped): the
+    grey values beside the projected axis.  Pixel u spans [u - 1/2, u + 1/2]
+    and is split at the centre in proportion, so an object symmetric about the
+    axis gives equal sums wherever the axis falls."""
+    out = np.zeros((len(projs), 2))
+    for k, p in enumerate(projs):
+        H, W = p.shape
+        a, b = max(0, int(row_lo[k])), min(H - 1, int(row_hi[k]))
+        if a > b:
+            continue
+        u = np.arange(W)
+        f_left = np.clip(centres[k] - (u - 0.5), 0.0, 1.0)
+        col = np.asarray(p[a:b + 1], dtype=np.float64).sum(axis=0)
+        out[k, 0] = (col * f_left).sum()
+        out[k, 1] = (col * (1.0 - f_left)).sum()
+    return out
+
+
+def azimuth_phase(s, s_ref):
+    """The internal rotation a maximising the circular cross-correlation
+    C(t) = integral s(phi) s_ref(phi + t) dphi of two signals sampled at the N
+    equally spaced view angles of a full circular trajectory (phi_k = phi_0 +
+    2 pi k / N).  Shifting the view angle is rotating the object about the
+    rotation axis, so the measured grey-value signal is the reference one
+    advanced by the object's internal rotation (Sec. 2.1, azimuthal phase; the
+    reference is projected with the same axis pose, which carries the tilt
+    correction of Eq. 5).  With the discrete Fourier coefficients S_m, R_m
+    (m = 1 .. floor((N-1)/2)), C(t) = sum_m 2 |S_m R_m| cos(m t - arg(S_m conj R_m));
+    its maximum on a 0.1-degree grid is refined by Newton steps."""
+    s = np.asarray(s, float)
+    r = np.asarray(s_ref, float)
+    N = s.size
+    S = np.fft.rfft(s)
+    R = np.fft.rfft(r)
+    M = (N - 1) // 2
+    m = np.arange(1, M + 1)
+    X = S[1:M + 1] * np.conj(R[1:M + 1])
+    amp, th = 2 * np.abs(X), np.angle(X)
+    taus = np.arange(3600) * (2 * np.pi / 3600)
+    C = (amp[None, :] * np.cos(np.outer(taus, m) - th[None, :])).sum(axis=1)
+    t = taus[int(np.argmax(C))]
+    for _ in range(8):
+        d1 = -(amp * m * np.sin(m * t - th)).sum()
+        d2 = -(amp * m * m * np.cos(m * t - th)).sum()
+        if d2 >= 0:
+            break
+        t -= d1 / d2
+    return float(np.mod(t, 2 * np.pi))
