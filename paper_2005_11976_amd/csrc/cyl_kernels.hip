@@ -875,9 +875,15 @@ __device__ __forceinline__ int slot(const Block &B, int h, int t, int q) {
 
 __device__ __forceinline__ int block_slots(const Block &B) { return slot(B, B.hB - B.hA, 0, 0) + 1; }
 
+// COLSUM = false: c_m += t_jm y_j into FP32 accumulators acc_c (LDS float atomics).
+// COLSUM = true (SART): c_m and n_m in one 64-bit fixed-point accumulator per
+// cell, acc64 = c 2^32 + n with c = sum rint(t_jm y_j cscale) and
+// n = sum rint(t_jm nscale): one integer LDS atomic per step, and integer sums
+// do not depend on their order.  The scales keep |c| and n below 2^30 (see
+// bp_kernel), so the low word never carries into the high word; ycs = y_j cscale.
 template <bool COLSUM>
 __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const ViewDev &V, const Block &B, int u,
-                                       int v, float yj, float *acc_c, int *acc_n, float nscale) {
+                                       int v, float yj, float *acc_c, unsigned long long *acc64, float nscale) {
     RayF r;
     double dx, dy, dz, tc;
     ray_geom<false>(g, T, V, u, v, r, dx, dy, dz, tc);  // the block clip bounds the walk
@@ -900,33 +906,28 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Vi
             }
         }
     }
-    // c accumulates with a float LDS atomic.  The column sum n, which depends on
-    // the geometry only, accumulates in fixed point with an integer LDS atomic
-    // (far cheaper than a second float atomic on gfx950), issued at the end of
-    // the step; nscale bounds the sum below 2^31 (see bp_kernel).  The walk is
-    // boxed to the block, so every visited cell has a slot:
+    // The walk is boxed to the block, so every visited cell has a slot:
     // slot = h ps + t rs + q - (hA ps + tA rs + rA), folded into the bases.
     const int rs = (B.rB - B.rA) + 1;
     const int ps = (B.tB - B.tA) * rs + 1;
     const int off = B.hA * ps + B.tA * rs + B.rA;
     struct Scatter {
         float *cb;
-        int *nb;
+        unsigned long long *b64;
         int ps, rs;
         float yj, nscale;
-        int nloc;
-        float nlen;
         __device__ __forceinline__ void operator()(int h, int t, int q, float len) {
             const int loc = (int)(__umul24(h, ps) + __umul24(t, rs)) + q;
-            atomicAdd(&cb[loc], len * yj);
-            nloc = loc;
-            nlen = len;
+            if (COLSUM) {
+                const unsigned int c = (unsigned int)__float2int_rn(len * yj);
+                const unsigned int n = (unsigned int)__float2int_rn(len * nscale);
+                atomicAdd(&b64[loc], ((unsigned long long)c << 32) | n);
+            } else {
+                atomicAdd(&cb[loc], len * yj);
+            }
         }
-        __device__ __forceinline__ void late() {
-            if (COLSUM && nlen != 0.0f) atomicAdd(&nb[nloc], __float2int_rn(nlen * nscale));
-            nlen = 0.0f;
-        }
-    } visit{acc_c - off, acc_n - off, ps, rs, yj, nscale, 0, 0.0f};
+        __device__ __forceinline__ void late() {}
+    } visit{acc_c - off, acc64 - off, ps, rs, yj, nscale};
     const Box bx{B.hA, B.hB - B.hA, B.tA, B.tB - B.tA, B.rA, B.rB - B.rA};
     for (int piece = 0; piece < 2; ++piece) {
         const float a0 = piece ? pb0 : pa0, a1 = piece ? pb1 : pa1;
@@ -969,8 +970,9 @@ __global__ __launch_bounds__(256) void bp_kernel(const BpLaunch L) {
     const Tabs T = stage_tables(g, smem, false);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int slots = g.bh * (g.bt * (g.br + 1) + 1) + 1;
+    // MODE 0: one float per slot; MODE 1: one 64-bit (c, n) word per slot (8-byte aligned)
     float *acc_c = (float *)(smem + table_floats2(g, false)) + wave * slots * (MODE == 1 ? 2 : 1);
-    int *acc_n = (int *)(acc_c + slots);
+    unsigned long long *acc64 = (unsigned long long *)acc_c;
     // dispatch order: outer rings first (their blocks carry the most work), and
     // the 4 waves of a workgroup take 4 blocks stacked in h (similar work, so
     // the workgroup's LDS is not held by one slow wave)
@@ -986,15 +988,18 @@ __global__ __launch_bounds__(256) void bp_kernel(const BpLaunch L) {
     const int ncell = (B.hB - B.hA) * wt * wr;
     const int nslot = block_slots(B);
     for (int i = lane; i < nslot; i += 64) {
-        acc_c[i] = 0.0f;
-        if (MODE == 1) acc_n[i] = 0;
+        if (MODE == 1)
+            acc64[i] = 0ull;
+        else
+            acc_c[i] = 0.0f;
     }
-    // fixed-point scale of the column sums (SART launches one view): any chord
-    // through a cell is at most the cell diameter D, and at most npix rays of
-    // the footprint box reach a cell, so n <= D npix; scale that bound to 2^30
+    // fixed-point scales (SART launches one view): any chord through a cell is
+    // at most the cell diameter D, and at most npix rays of the footprint box
+    // reach a cell, so n <= D npix and |c| <= D npix max|rho| over the box;
+    // each bound is scaled to at most 2^30
     const float ctheta = (B.tB - B.tA) * g.dtheta >= 3.14159265f ? 2.0f : 2.0f * sinf(0.5f * (B.tB - B.tA) * g.dtheta);
     const float dcell = sqrtf(g.dh * g.dh + (g.dr + T.r[B.rB].x * ctheta) * (g.dr + T.r[B.rB].x * ctheta)) * 1.001f;
-    float nscale = 1.0f, inv_nscale = 1.0f;
+    float nscale = 1.0f, inv_nscale = 1.0f, cscale = 1.0f, inv_cscale = 1.0f;
     __syncthreads();
     if (live) {
         for (int k = view_begin; k < view_end; ++k) {
@@ -1012,6 +1017,15 @@ __global__ __launch_bounds__(256) void bp_kernel(const BpLaunch L) {
                 frexpf(1073741824.0f / (dcell * (float)npix), &e);
                 nscale = ldexpf(1.0f, e - 1);
                 inv_nscale = ldexpf(1.0f, 1 - e);
+                float rmax = 0.0f;
+                for (int p = lane; p < npix; p += 64)
+                    rmax = fmaxf(rmax, fabsf(rho[(size_t)(v0 + p / nu) * g.cols + u0 + p % nu]));
+                rmax = wave_max(rmax);
+                if (rmax > 0.0f) {
+                    frexpf(1073741824.0f / (dcell * (float)npix * rmax), &e);
+                    cscale = ldexpf(1.0f, e - 1);
+                    inv_cscale = ldexpf(1.0f, 1 - e);
+                }
             }
             for (int base = 0; base < npix; base += 64) {
                 const int p = base + lane;
@@ -1024,7 +1038,7 @@ __global__ __launch_bounds__(256) void bp_kernel(const BpLaunch L) {
                 else
                     yj = Store<PT>::ld(y, ((size_t)k * g.rows + v) * g.cols + u);
                 if (MODE == 0 && yj == 0.0f) continue;
-                bp_ray<(MODE == 1)>(g, T, V, B, u, v, yj, acc_c, acc_n, nscale);
+                bp_ray<(MODE == 1)>(g, T, V, B, u, v, MODE == 1 ? yj * cscale : yj, acc_c, acc64, nscale);
             }
         }
     }
@@ -1040,10 +1054,12 @@ __global__ __launch_bounds__(256) void bp_kernel(const BpLaunch L) {
             const float base = accumulate ? Store<VT>::ld(vol, gi) : 0.0f;
             Store<VT>::st(vol, gi, base + acc_c[sl]);
         } else {
-            const float n = (float)acc_n[sl] * inv_nscale;
+            const unsigned long long a = acc64[sl];
+            const float n = (float)(unsigned int)a * inv_nscale;
             if (n > 0.0f) {
+                const float c = (float)(int)(unsigned int)(a >> 32) * inv_cscale;
                 const float w = vw ? ld_any(vw, vwt, gi) : 1.0f;
-                float m = Store<VT>::ld(vol, gi) + lam * w * acc_c[sl] / n;
+                float m = Store<VT>::ld(vol, gi) + lam * w * c / n;
                 if (nonneg && m < 0.0f) m = 0.0f;
                 Store<VT>::st(vol, gi, m);
             }
