@@ -268,6 +268,30 @@ int cyl_track_point(const cyl_traj *traj, const double *uv, const uint8_t *valid
 int cyl_pose_from_axis(const double *top, const double *bottom, double h_top, double h_bottom, double alpha,
                        cyl_pose *out);
 
+/* Grey values beside the projected axis (Sec. 2.1, azimuthal phase): for each
+ * view k, over rows [row_lo[k], row_hi[k]] (clipped to the detector),
+ * sums[2k] = sum of the pixels left of detector position centre[k] and
+ * sums[2k+1] = sum right of it; pixel u spans [u - 1/2, u + 1/2] and is split
+ * at the centre in proportion.  All arrays are device memory: proj
+ * [n_views][rows][cols] of proj_type, centre float64 [n_views], row_lo/row_hi
+ * int32 [n_views], sums float64 [n_views][2].  FP64 accumulation in a fixed
+ * order (reproducible).  CYL_EINVAL for bad sizes or NULL buffers. */
+int cyl_side_sums(int32_t n_views, int32_t rows, int32_t cols, const void *proj, cyl_dtype proj_type,
+                  const double *centre, const int32_t *row_lo, const int32_t *row_hi, double *sums,
+                  int32_t device, void *hip_stream);
+
+/* Internal rotation angle (Sec. 2.1, Eq. 5) from a measured grey-value signal s
+ * and a reference signal s_ref, both sampled at the n equally spaced view
+ * angles of a full circular trajectory, the reference projected with the same
+ * axis pose and no internal rotation: the angle a in [0, 2 pi) maximising the
+ * circular cross-correlation of s(phi) and s_ref(phi + a) (a view-angle shift
+ * is a rotation of the object about the rotation axis; the reference carries
+ * the tilt correction of Eq. 5).  Trigonometric interpolation through the
+ * discrete Fourier coefficients m = 1 .. (n-1)/2, best of a 0.1-degree grid
+ * refined by Newton steps.  Host call.  CYL_EINVAL for n < 3, NULL arrays or
+ * non-finite values. */
+int cyl_azimuth_phase(int32_t n, const double *s, const double *s_ref, double *alpha);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *cyl_last_error(void);
 

@@ -93,11 +93,81 @@ __global__ __launch_bounds__(256) void axis_corner_kernel(const void *__restrict
     o[7] = (int32_t)v;
 }
 
+// Per view: grey values left and right of the detector position centre[view]
+// over rows [row_lo, row_hi]; pixel u spans [u - 1/2, u + 1/2] and is split
+// at the centre in proportion.  FP64 sums in a fixed order (per-thread
+// partials, then a tree), so the result does not vary between runs.
+__global__ __launch_bounds__(256) void side_sum_kernel(const void *__restrict__ proj, int pt, int rows, int cols,
+                                                       const double *__restrict__ centre,
+                                                       const int32_t *__restrict__ row_lo,
+                                                       const int32_t *__restrict__ row_hi, double *__restrict__ out) {
+    const int view = blockIdx.x;
+    const double c = centre[view];
+    const int a = row_lo[view] < 0 ? 0 : row_lo[view];
+    const int b = row_hi[view] >= rows ? rows - 1 : row_hi[view];
+    const size_t base = (size_t)view * rows * cols;
+    double left = 0.0, right = 0.0;
+    if (a <= b) {
+        const size_t n = (size_t)(b - a + 1) * cols;
+        for (size_t j = threadIdx.x; j < n; j += blockDim.x) {
+            const int u = (int)(j % cols);
+            const double val = (double)load_any(proj, pt, base + (size_t)a * cols + j);
+            double f = c - ((double)u - 0.5);
+            f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+            left += f * val;
+            right += (1.0 - f) * val;
+        }
+    }
+    __shared__ double red[2][256];
+    red[0][threadIdx.x] = left;
+    red[1][threadIdx.x] = right;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * view] = red[0][0];
+        out[2 * view + 1] = red[1][0];
+    }
+}
+
 }  // namespace
 
 }  // namespace cyl
 
 using namespace cyl;
+
+extern "C" int cyl_side_sums(int32_t n_views, int32_t rows, int32_t cols, const void *proj, cyl_dtype proj_type,
+                             const double *centre, const int32_t *row_lo, const int32_t *row_hi, double *sums,
+                             int32_t device, void *hip_stream) {
+    if (n_views < 0 || rows < 1 || cols < 1 ||
+        (n_views > 0 && (!proj || !centre || !row_lo || !row_hi || !sums))) {
+        set_error("cyl_side_sums: need n_views >= 0, rows, cols >= 1 and non-NULL buffers");
+        return CYL_EINVAL;
+    }
+    int rc;
+    if ((rc = check_dtype(proj_type, "cyl_side_sums projections"))) return rc;
+    if (n_views == 0) return CYL_OK;
+    int prev = -1;
+    hipGetDevice(&prev);
+    if (prev != device && hipSetDevice(device) != hipSuccess) {
+        set_error("cyl_side_sums: cannot select device %d", device);
+        return CYL_EDEVICE;
+    }
+    hipLaunchKernelGGL(side_sum_kernel, dim3(n_views), dim3(256), 0, (hipStream_t)hip_stream, proj,
+                       (int)proj_type, rows, cols, centre, row_lo, row_hi, sums);
+    hipError_t e = hipGetLastError();
+    if (prev >= 0 && prev != device) hipSetDevice(prev);
+    if (e != hipSuccess) {
+        set_error("cyl_side_sums: launch failed: %s", hipGetErrorString(e));
+        return CYL_EDEVICE;
+    }
+    return CYL_OK;
+}
 
 extern "C" int cyl_axis_corners(int32_t n_views, int32_t rows, int32_t cols, const void *proj, cyl_dtype proj_type,
                                 double threshold, int32_t dilate, int32_t *corners, int32_t device,

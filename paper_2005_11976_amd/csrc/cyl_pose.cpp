@@ -218,3 +218,57 @@ extern "C" int cyl_pose_from_axis(const double *top, const double *bottom, doubl
         out->T[r] = -(out->R[3 * r] * centre[0] + out->R[3 * r + 1] * centre[1] + out->R[3 * r + 2] * centre[2]);
     return CYL_OK;
 }
+
+extern "C" int cyl_azimuth_phase(int32_t n, const double *s, const double *s_ref, double *alpha) {
+    if (n < 3 || !s || !s_ref || !alpha) {
+        set_error("cyl_azimuth_phase: need n >= 3 and non-NULL arrays");
+        return CYL_EINVAL;
+    }
+    for (int k = 0; k < n; ++k)
+        if (!std::isfinite(s[k]) || !std::isfinite(s_ref[k])) {
+            set_error("cyl_azimuth_phase: non-finite signal value at %d", k);
+            return CYL_EINVAL;
+        }
+    // cross-power X_m = S_m conj(R_m) of the DFTs (S_m = sum_k s_k e^{-2 pi i m k / n})
+    const int M = (n - 1) / 2;
+    std::vector<double> amp(M), th(M);
+    for (int m = 1; m <= M; ++m) {
+        double sr = 0, si = 0, rr = 0, ri = 0;
+        for (int k = 0; k < n; ++k) {
+            const double a = -2.0 * M_PI * (double)((long long)m * k % n) / n;
+            const double ca = std::cos(a), sa = std::sin(a);
+            sr += s[k] * ca;
+            si += s[k] * sa;
+            rr += s_ref[k] * ca;
+            ri += s_ref[k] * sa;
+        }
+        const double xr = sr * rr + si * ri, xi = si * rr - sr * ri;
+        amp[m - 1] = 2.0 * std::hypot(xr, xi);
+        th[m - 1] = std::atan2(xi, xr);
+    }
+    // C(t) = sum_m amp_m cos(m t - th_m): best of a 0.1-degree grid, then Newton
+    double best_t = 0.0, best_c = -INFINITY;
+    for (int i = 0; i < 3600; ++i) {
+        const double t = 2.0 * M_PI * i / 3600.0;
+        double c = 0.0;
+        for (int m = 1; m <= M; ++m) c += amp[m - 1] * std::cos(m * t - th[m - 1]);
+        if (c > best_c) {
+            best_c = c;
+            best_t = t;
+        }
+    }
+    double t = best_t;
+    for (int it = 0; it < 8; ++it) {
+        double d1 = 0.0, d2 = 0.0;
+        for (int m = 1; m <= M; ++m) {
+            d1 -= amp[m - 1] * m * std::sin(m * t - th[m - 1]);
+            d2 -= amp[m - 1] * m * m * std::cos(m * t - th[m - 1]);
+        }
+        if (!(d2 < 0.0)) break;
+        t -= d1 / d2;
+    }
+    t = std::fmod(t, 2.0 * M_PI);
+    if (t < 0.0) t += 2.0 * M_PI;
+    *alpha = t;
+    return CYL_OK;
+}

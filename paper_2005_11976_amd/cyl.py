@@ -20,7 +20,7 @@ CYL_OK, CYL_EINVAL, CYL_ENOMEM, CYL_EDEVICE, CYL_EUNSUPPORTED = 0, -1, -2, -3, -
 EXPORTS = ["cyl_geom_create", "cyl_geom_destroy", "cyl_fp", "cyl_bp", "cyl_row_sums",
            "cyl_sart_workspace_bytes", "cyl_sart_run", "cyl_sart_residual", "cyl_sart_update",
            "cyl_sart_batch_step", "cyl_fp_diff", "cyl_add", "cyl_axis_corners", "cyl_track_point",
-           "cyl_pose_from_axis", "cyl_last_error", "cyl_version"]
+           "cyl_pose_from_axis", "cyl_side_sums", "cyl_azimuth_phase", "cyl_last_error", "cyl_version"]
 
 
 class CylError(RuntimeError):
@@ -98,6 +98,10 @@ def declare(lib):
     lib.cyl_pose_from_axis.argtypes = [P(C.c_double), P(C.c_double), C.c_double, C.c_double, C.c_double,
                                        P(cyl_pose)]
     lib.cyl_pose_from_axis.restype = C.c_int
+    lib.cyl_side_sums.argtypes = [i32, i32, i32, vp, C.c_int, vp, vp, vp, vp, i32, vp]
+    lib.cyl_side_sums.restype = C.c_int
+    lib.cyl_azimuth_phase.argtypes = [i32, P(C.c_double), P(C.c_double), P(C.c_double)]
+    lib.cyl_azimuth_phase.restype = C.c_int
     lib.cyl_last_error.argtypes = []
     lib.cyl_last_error.restype = C.c_char_p
     lib.cyl_version.argtypes = []
@@ -431,3 +435,35 @@ def pose_from_axis(top, bottom, h_top, h_bottom, alpha, _lib=None):
     out = cyl_pose()
     _check(L.cyl_pose_from_axis(t, b, float(h_top), float(h_bottom), float(alpha), C.byref(out)), L)
     return np.array(out.R[:]).reshape(3, 3), np.array(out.T[:])
+
+
+def side_sums(proj, centre, row_lo, row_hi, stream=None, _lib=None):
+    """cyl_side_sums on a [n, rows, cols] CUDA tensor; centre, row_lo, row_hi
+    host sequences of length n.  Returns a float64 CUDA tensor [n, 2]."""
+    import torch
+    L = _lib or lib()
+    if proj.dim() != 3 or not (proj.is_cuda and proj.is_contiguous()):
+        raise ValueError("projections must be a contiguous CUDA tensor [n_views, rows, cols]")
+    n, rows, cols = proj.shape
+    dev = proj.device
+    c = torch.as_tensor(np.asarray(centre, dtype=np.float64).reshape(n), device=dev).contiguous()
+    lo = torch.as_tensor(np.asarray(row_lo, dtype=np.int32).reshape(n), device=dev).contiguous()
+    hi = torch.as_tensor(np.asarray(row_hi, dtype=np.int32).reshape(n), device=dev).contiguous()
+    out = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    _check(L.cyl_side_sums(n, rows, cols, C.c_void_p(proj.data_ptr()), _dtype_code(proj),
+                           C.c_void_p(c.data_ptr()), C.c_void_p(lo.data_ptr()), C.c_void_p(hi.data_ptr()),
+                           C.c_void_p(out.data_ptr()), dev.index or 0, _stream_ptr(stream)), L)
+    return out
+
+
+def azimuth_phase(s, s_ref, _lib=None):
+    """cyl_azimuth_phase (host): internal rotation angle in [0, 2 pi)."""
+    L = _lib or lib()
+    a = np.ascontiguousarray(s, dtype=np.float64)
+    b = np.ascontiguousarray(s_ref, dtype=np.float64)
+    if a.shape != b.shape or a.ndim != 1:
+        raise ValueError("signals must be 1-D and of equal length")
+    out = C.c_double()
+    _check(L.cyl_azimuth_phase(a.size, a.ctypes.data_as(C.POINTER(C.c_double)),
+                               b.ctypes.data_as(C.POINTER(C.c_double)), C.byref(out)), L)
+    return out.value

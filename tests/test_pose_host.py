@@ -61,3 +61,21 @@ def test_pose_from_axis_matches_reference_and_truth(cyl):
         cyl.pose_from_axis(top, top, 1.0, 0.0, 0.0)
     with pytest.raises(cyl.CylError):
         cyl.pose_from_axis(top, bot, 0.0, 1.0, 0.0)
+
+
+def test_azimuth_phase_matches_reference(cyl):
+    rng = np.random.default_rng(17)
+    for n in (36, 72, 91, 120):
+        phi = np.arange(n) * (2 * np.pi / n)
+        coef = rng.normal(size=(6, 2))
+        def sig(x):
+            return sum(c[0] * np.cos((m + 1) * x) + c[1] * np.sin((m + 1) * x) for m, c in enumerate(coef)) + 0.7
+        for a in (0.3, 2.2, 4.9):
+            s, r = sig(phi + a), sig(phi)
+            got = cyl.azimuth_phase(s, r)
+            assert abs(got - P.azimuth_phase(s, r)) < 1e-9
+            assert abs((got - a + np.pi) % (2 * np.pi) - np.pi) < 1e-8
+    with pytest.raises(cyl.CylError):
+        cyl.azimuth_phase(np.zeros(2), np.zeros(2))
+    with pytest.raises(cyl.CylError):
+        cyl.azimuth_phase(np.array([0.0, np.nan, 1.0]), np.zeros(3))
