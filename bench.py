@@ -28,9 +28,9 @@ HBM_PEAK_GBS = 8000.0
 # device copy, taken on the kernel sources whose sha256 prefix is given here
 # (profiles/fp_bp_sart_single_256x720x128_hbm_counters.md). For any other
 # source, or another storage type, the traffic is reported as null.
-MEASURED_TRAFFIC = {"src_sha": "b5e7e36be6274ecb",
-                    "fp_residual": 108210227 + 1529859,
-                    "bp_update": 189096711 + 93193984}
+MEASURED_TRAFFIC = {"src_sha": "b5b327d6b48f4759",
+                    "fp_residual": 136111709 + 1222467,
+                    "bp_update": 341068835 + 100911102}
 
 
 def kernel_src_sha():
