@@ -906,6 +906,16 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Vi
             }
         }
     }
+    // Walk the first non-empty piece first: most rays that meet the hole have
+    // only the piece after it, and a ray with two pieces is rare (nearly
+    // tangent to r_A within the wedge), so the second walk is then skipped by
+    // whole waves instead of idling every lane whose piece came first.
+    if (!(pa1 > pa0)) {
+        pa0 = pb0;
+        pa1 = pb1;
+        pb0 = 1.0f;
+        pb1 = 0.0f;
+    }
     // The walk is boxed to the block, so every visited cell has a slot:
     // slot = h ps + t rs + q - (hA ps + tA rs + rA), folded into the bases.
     const int rs = (B.rB - B.rA) + 1;
