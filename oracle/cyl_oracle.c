@@ -11,9 +11,10 @@
  *                                                                    (Eq. 2)
  *   - system matrix:  t_jl = length of ray j (source -> pixel centre)
  *                     inside ring-sector cell l                      (Eq. 6)
- *   - SART:           per projection, mu_m += lam * w_m *
+ *   - SART:           per ordered subset (one projection, or several;
+ *                     all of them is SIRT), mu_m += lam * w_m *
  *                     sum_j t_jm * wp_j (p_j - sum_l t_jl mu_l) / sum_l t_jl
- *                     / sum_j t_jm                                   (Eq. 7)
+ *                     / sum_j t_jm, j over the rays of the subset    (Eq. 7)
  *                     with the voxel weight map w_m of the weighted back-
  *                     projection (Sec. 2.2, last paragraph).
  *
@@ -329,51 +330,79 @@ typedef struct {
     int32_t nonneg;
     const int32_t *view_order; /* NULL = 0..n_views-1 */
     int32_t start_iter, start_view;
+    int32_t subset; /* projections per ordered subset; <= 1: one (plain SART) */
 } orc_sart_params;
 
 /*
- * Sequential weighted SART, Eq. 7 with one projection per update step.
+ * Weighted SART, Eq. 7, with ordered subsets of `subset` projections: the
+ * view order is cut into consecutive groups of `subset` positions (the last
+ * one may be shorter), and each group is one update step.  All views of a
+ * group are projected from the same mu, their residuals rho_j are formed, and
+ * c_m = sum_j t_jm rho_j and n_m = sum_j t_jm run over every ray of the group
+ * before mu_m += lam w_m c_m / n_m.  subset = 1 is the paper's setting (one
+ * projection per update); subset = n_views is SIRT.
  * vol: in = prior mu(0), out = result.  proj: (views, rows, cols) measured
  * line integrals.  pw: per-pixel weights or NULL (= 1).  vw: per-voxel
  * weights or NULL (= 1).  If resid_out is non-NULL it receives, per
  * iteration, sum_j (p_j - q_j)^2 over all views as seen during the sweep.
- * The resume point (start_iter, start_view) counts positions in view_order.
+ * The resume point (start_iter, start_view) counts positions in view_order
+ * and must fall on a group boundary.
  */
 int orc_sart(const orc_scan *s, const orc_sart_params *P, const double *proj, const double *pw,
              const double *vw, double *vol, double *resid_out, int nthreads) {
     int64_t V = (int64_t)s->g.n_h * s->g.n_theta * s->g.n_r;
     int64_t per_view = (int64_t)s->det_rows * s->det_cols;
+    int m = P->subset > 1 ? P->subset : 1;
+    if (m > s->n_views) m = s->n_views;
+    if (m < 1) m = 1;
     double *q = (double *)malloc(sizeof(double) * per_view);
     double *L = (double *)malloc(sizeof(double) * per_view);
-    double *rho = (double *)malloc(sizeof(double) * per_view);
+    double *rho = (double *)malloc(sizeof(double) * per_view * m);
     double *c = (double *)malloc(sizeof(double) * V);
     double *nsum = (double *)malloc(sizeof(double) * V);
-    if (!q || !L || !rho || !c || !nsum) return -2;
+    double *ck = (double *)malloc(sizeof(double) * V);
+    double *nk = (double *)malloc(sizeof(double) * V);
+    if (!q || !L || !rho || !c || !nsum || !ck || !nk) return -2;
     for (int it = P->start_iter; it < P->n_iter; ++it) {
         double r2 = 0.0;
         int kv0 = (it == P->start_iter) ? P->start_view : 0;
-        for (int kk = kv0; kk < s->n_views; ++kk) {
-            int k = P->view_order ? P->view_order[kk] : kk;
-            orc_fp(s, vol, k, k + 1, q, L, nthreads);
-            const double *p = proj + per_view * (size_t)k;
-            for (int64_t j = 0; j < per_view; ++j) {
-                double res = p[j] - q[j];
-                r2 += res * res;
-                double w = pw ? pw[per_view * (size_t)k + j] : 1.0;
-                rho[j] = (L[j] > 0.0) ? w * res / L[j] : 0.0;
+        for (int g0 = kv0; g0 < s->n_views; g0 += m) {
+            int cnt = s->n_views - g0 < m ? s->n_views - g0 : m;
+            /* residuals of every view of the group, from the same mu */
+            for (int i = 0; i < cnt; ++i) {
+                int k = P->view_order ? P->view_order[g0 + i] : g0 + i;
+                orc_fp(s, vol, k, k + 1, q, L, nthreads);
+                const double *p = proj + per_view * (size_t)k;
+                double *rk = rho + per_view * (size_t)i;
+                for (int64_t j = 0; j < per_view; ++j) {
+                    double res = p[j] - q[j];
+                    r2 += res * res;
+                    double w = pw ? pw[per_view * (size_t)k + j] : 1.0;
+                    rk[j] = (L[j] > 0.0) ? w * res / L[j] : 0.0;
+                }
             }
-            orc_bp(s, rho, k, k + 1, c, nsum, nthreads);
-            for (int64_t m = 0; m < V; ++m) {
-                if (!(nsum[m] > 0.0)) continue;
-                double w = vw ? vw[m] : 1.0;
-                double nv = vol[m] + P->lambda * w * c[m] / nsum[m];
+            /* column sums over all rays of the group */
+            for (int i = 0; i < cnt; ++i) {
+                int k = P->view_order ? P->view_order[g0 + i] : g0 + i;
+                double *cc = i == 0 ? c : ck, *nn = i == 0 ? nsum : nk;
+                orc_bp(s, rho + per_view * (size_t)i, k, k + 1, cc, nn, nthreads);
+                if (i > 0)
+                    for (int64_t l = 0; l < V; ++l) {
+                        c[l] += ck[l];
+                        nsum[l] += nk[l];
+                    }
+            }
+            for (int64_t l = 0; l < V; ++l) {
+                if (!(nsum[l] > 0.0)) continue;
+                double w = vw ? vw[l] : 1.0;
+                double nv = vol[l] + P->lambda * w * c[l] / nsum[l];
                 if (P->nonneg && nv < 0.0) nv = 0.0;
-                vol[m] = nv;
+                vol[l] = nv;
             }
         }
         if (resid_out) resid_out[it] = r2;
     }
-    free(q); free(L); free(rho); free(c); free(nsum);
+    free(q); free(L); free(rho); free(c); free(nsum); free(ck); free(nk);
     return 0;
 }
 

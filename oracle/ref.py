@@ -42,7 +42,7 @@ class _Scan(C.Structure):
 class _SartParams(C.Structure):
     _fields_ = [("n_iter", C.c_int32), ("lam", C.c_double), ("nonneg", C.c_int32),
                 ("view_order", C.POINTER(C.c_int32)), ("start_iter", C.c_int32),
-                ("start_view", C.c_int32)]
+                ("start_view", C.c_int32), ("subset", C.c_int32)]
 
 
 _lib = None
@@ -143,7 +143,9 @@ class Oracle:
 
     # -- SART -----------------------------------------------------------------
     def sart(self, proj, vol0, n_iter, lam=0.5, proj_weights=None, vox_weights=None,
-             nonneg=False, view_order=None, start_iter=0, start_view=0, nthreads=None):
+             nonneg=False, view_order=None, start_iter=0, start_view=0, nthreads=None, subset=1):
+        """Weighted SART (Eq. 7) with ordered subsets of `subset` projections
+        (1: one projection per update, the paper's setting; n_views: SIRT)."""
         p = _f64(proj).ravel()
         assert p.size == self.scan.n_views * self.P
         vol = _f64(vol0).ravel().copy()
@@ -156,6 +158,7 @@ class Oracle:
             order = np.ascontiguousarray(view_order, dtype=np.int32)
             prm.view_order = order.ctypes.data_as(C.POINTER(C.c_int32))
         prm.start_iter, prm.start_view = start_iter, start_view
+        prm.subset = int(subset)
         resid = np.zeros(max(n_iter, 1))
         rc = lib().orc_sart(C.byref(self._st), C.byref(prm), _dp(p),
                             _dp(pw) if pw is not None else None,
