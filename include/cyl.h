@@ -160,6 +160,30 @@ int cyl_sart_run(const cyl_geom *geom, const cyl_sart_params *params, const void
                  cyl_dtype vol_type, void *workspace, size_t workspace_bytes,
                  void *hip_stream);
 
+/* Ordered-subset SART (Eq. 7 with an ordered subset of several projections;
+ * subset = n_views is SIRT).  Each iteration splits the view order into
+ * consecutive groups of `subset` positions (the last group may be shorter);
+ * per group, all its views are projected from the same mu, then
+ *   rho_j = wp_j (p_j - q_j) / L_j                  for every ray of the group
+ *   c_m   = sum_{j in group} t_jm rho_j,  n_m = sum_{j in group} t_jm
+ *   mu_m += lambda * wv_m * c_m / n_m   if n_m > 0  (rounded into vol_type)
+ * subset = 1 computes exactly what cyl_sart_run computes, bit for bit.
+ * Arguments as for cyl_sart_run, plus:
+ *   subset     views per update, >= 1 (values above n_views act as n_views);
+ *              subset x rows x cols must not exceed 2^28 rays
+ *   workspace  device buffer of at least cyl_os_sart_workspace_bytes(geom,
+ *              subset) bytes (one FP32 residual image per view of a group and
+ *              the view order), owned by the caller, not used by anything
+ *              else until the work completes
+ * A resume point (start_view) must fall on a group boundary.  Errors:
+ * CYL_EINVAL for bad arguments (nothing is launched), CYL_EDEVICE for launch
+ * failures. */
+size_t cyl_os_sart_workspace_bytes(const cyl_geom *geom, int32_t subset);
+int cyl_os_sart_run(const cyl_geom *geom, const cyl_sart_params *params, int32_t subset, const void *proj,
+                    cyl_dtype proj_type, const void *proj_weights, cyl_dtype proj_weights_type,
+                    const void *vox_weights, cyl_dtype vox_weights_type, void *vol, cyl_dtype vol_type,
+                    void *workspace, size_t workspace_bytes, void *hip_stream);
+
 /* The two kernels of one SART sub-iteration (Eq. 7, one view), for callers
  * that schedule views themselves (a serving loop interleaving scans, or a
  * profiler timing each kernel).  Running, for k in order,

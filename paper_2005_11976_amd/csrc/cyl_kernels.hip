@@ -114,6 +114,14 @@ __device__ __forceinline__ float vmax(float a, float b) {
 }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// floor(x + 1/2) as an integer in one instruction (round to nearest, ties
+// upward): the fixed-point sums need a fixed rounding rule, not a particular one.
+__device__ __forceinline__ int round_half_up(float x) {
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 // ------------------------------------------------------------ grid tables
 
 // Grid tables as seen by a kernel (staged in LDS by every workgroup).
@@ -572,10 +580,12 @@ struct FpLaunch {
 
 struct BpItem {
     GeomDev g;
-    const void *y;        // projections (plain) or FP32 residual image (SART)
+    const void *y;        // projections (plain) or FP32 residual images (SART), one per position
     void *vol;
     const void *vw;       // voxel weights or null (SART)
-    int view_begin, view_end, nwg, accumulate, vwt, nonneg;
+    const int32_t *views; // SART: device list of views, position k -> views[k]; null: view k
+    int view_begin, view_end, nwg;
+    int flags;            // bit 0: accumulate (plain), bit 1: nonneg (SART), bits 8+: type of vw
     float lam;
 };
 struct BpLaunch {
@@ -734,7 +744,7 @@ __device__ __forceinline__ float wave_max(float x) {
 // front of the source.
 __device__ __forceinline__ void footprint_point(const GeomDev &g, const Tabs &T, const ViewDev &V, const Block &B,
                                                 int pt, float &umin, float &umax, float &vmin, float &vmax,
-                                                float &behind) {
+                                                float &behind, float &lmin) {
     const float rO = T.r[B.rB].x * (1.0f + 1e-6f) + 1e-6f;
     const float rI = T.r[B.rA].x;
     const bool full = (B.tB - B.tA) >= g.n_theta;
@@ -773,6 +783,7 @@ __device__ __forceinline__ void footprint_point(const GeomDev &g, const Tabs &T,
     const float vv = V.Qi[6] * X + V.Qi[7] * Y + V.Qi[8] * Z;
     if (lam > 1e-6f) {
         const float il = 1.0f / lam;
+        lmin = fminf(lmin, lam);
         umin = fminf(umin, uu * il);
         umax = fmaxf(umax, uu * il);
         vmin = fminf(vmin, vv * il);
@@ -805,17 +816,41 @@ __device__ __forceinline__ bool footprint_box(const GeomDev &g, float umin, floa
 }
 
 // Detector box of the block in view V; the whole wave participates (each lane
-// projects one hull point, then min/max across the wave).
+// projects one hull point, then min/max across the wave).  If cellrays is
+// given, it receives a bound on the number of rays of the box that meet any
+// one cell of diameter at most dcell: the box size, or fewer from the
+// projection's scale.  With X' = X - a, u = (q_u X') / (q_l X') and
+// v = (q_v X') / (q_l X') (q_* rows of Qi), so |du/dX| <= (|q_u| + |u| |q_l|) / lam
+// with lam = q_l X'; over the block hull (a convex prism inside the projected
+// polygon prism) |u| and 1/lam are largest at its vertices.  A cell's convex
+// hull lies in the block hull, so its image spans at most ext_u = dcell
+// max|du/dX| columns and ext_v rows, which hold at most
+// (ext_u + 1)(ext_v + 1) pixel centres.
 __device__ bool footprint(const GeomDev &g, const Tabs &T, const ViewDev &V, const Block &B, int &u0, int &u1,
-                          int &v0, int &v1) {
-    float umin = CYL_INF, umax = -CYL_INF, vmin = CYL_INF, vmax = -CYL_INF, behind = 0.0f;
-    footprint_point(g, T, V, B, threadIdx.x & 63, umin, umax, vmin, vmax, behind);
+                          int &v0, int &v1, float dcell = 0.0f, float *cellrays = nullptr) {
+    float umin = CYL_INF, umax = -CYL_INF, vmin = CYL_INF, vmax = -CYL_INF, behind = 0.0f, lmin = CYL_INF;
+    footprint_point(g, T, V, B, threadIdx.x & 63, umin, umax, vmin, vmax, behind, lmin);
     umin = wave_min(umin);
     umax = wave_max(umax);
     vmin = wave_min(vmin);
     vmax = wave_max(vmax);
     behind = wave_max(behind);
-    return footprint_box(g, umin, umax, vmin, vmax, behind, u0, u1, v0, v1);
+    const bool any = footprint_box(g, umin, umax, vmin, vmax, behind, u0, u1, v0, v1);
+    if (cellrays && any) {
+        float rays = (float)((u1 - u0 + 1) * (v1 - v0 + 1));
+        if (!(behind > 0.0f)) {
+            lmin = wave_min(lmin);
+            const float ql = sqrtf(V.Qi[0] * V.Qi[0] + V.Qi[1] * V.Qi[1] + V.Qi[2] * V.Qi[2]);
+            const float qu = sqrtf(V.Qi[3] * V.Qi[3] + V.Qi[4] * V.Qi[4] + V.Qi[5] * V.Qi[5]);
+            const float qv = sqrtf(V.Qi[6] * V.Qi[6] + V.Qi[7] * V.Qi[7] + V.Qi[8] * V.Qi[8]);
+            const float au = fmaxf(fabsf(umin), fabsf(umax)), av = fmaxf(fabsf(vmin), fabsf(vmax));
+            const float eu = dcell * (qu + au * ql) / lmin * 1.001f;
+            const float ev = dcell * (qv + av * ql) / lmin * 1.001f;
+            rays = fminf(rays, (floorf(eu) + 1.0f) * (floorf(ev) + 1.0f));
+        }
+        *cellrays = rays;
+    }
+    return any;
 }
 
 // Parameter interval of the ray inside the block hull (slab x wedge x disc),
@@ -929,8 +964,8 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Vi
         __device__ __forceinline__ void operator()(int h, int t, int q, float len) {
             const int loc = (int)(__umul24(h, ps) + __umul24(t, rs)) + q;
             if (COLSUM) {
-                const unsigned int c = (unsigned int)__float2int_rn(len * yj);
-                const unsigned int n = (unsigned int)__float2int_rn(len * nscale);
+                const unsigned int c = (unsigned int)round_half_up(len * yj);
+                const unsigned int n = (unsigned int)round_half_up(len * nscale);
                 atomicAdd(&b64[loc], ((unsigned long long)c << 32) | n);
             } else {
                 atomicAdd(&cb[loc], len * yj);
@@ -962,8 +997,9 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Vi
 // views, over the detector pixels of the block footprint, traces each ray
 // through the block hull and accumulates c_m = sum t_jm y_j and
 // n_m = sum t_jm in wave-private LDS (deterministic: no wave shares a slot).
-// MODE 0: vol = (accumulate ? vol : 0) + c.  MODE 1 (SART, one view):
-// vol += lam * wv * c / n where n > 0.
+// MODE 0: vol = (accumulate ? vol : 0) + c.  MODE 1 (SART, the views of one
+// ordered subset, c and n summed over all their rays): vol += lam * wv * c / n
+// where n > 0.
 template <int VT, int PT, int MODE>
 __global__ __launch_bounds__(256) void bp_kernel(const BpLaunch L) {
     const BpItem &item = L.item[blockIdx.y];
@@ -974,7 +1010,7 @@ __global__ __launch_bounds__(256) void bp_kernel(const BpLaunch L) {
     void *__restrict__ vol = item.vol;
     const void *__restrict__ vw = item.vw;
     const int view_begin = item.view_begin, view_end = item.view_end;
-    const int accumulate = item.accumulate, vwt = item.vwt, nonneg = item.nonneg;
+    const int accumulate = item.flags & 1, nonneg = (item.flags >> 1) & 1, vwt = item.flags >> 8;
     const float lam = item.lam;
     extern __shared__ float2 smem[];
     const Tabs T = stage_tables(g, smem, false);
@@ -1003,40 +1039,85 @@ __global__ __launch_bounds__(256) void bp_kernel(const BpLaunch L) {
         else
             acc_c[i] = 0.0f;
     }
-    // fixed-point scales (SART launches one view): any chord through a cell is
-    // at most the cell diameter D, and at most npix rays of the footprint box
-    // reach a cell, so n <= D npix and |c| <= D npix max|rho| over the box;
-    // each bound is scaled to at most 2^30
-    const float ctheta = (B.tB - B.tA) * g.dtheta >= 3.14159265f ? 2.0f : 2.0f * sinf(0.5f * (B.tB - B.tA) * g.dtheta);
-    const float dcell = sqrtf(g.dh * g.dh + (g.dr + T.r[B.rB].x * ctheta) * (g.dr + T.r[B.rB].x * ctheta)) * 1.001f;
+    // fixed-point scales, common to the views of one update.  The length of a
+    // ray inside one cell is at most the cell's diameter D, and view k has at
+    // most R_k rays that meet a given cell (the footprint box's pixels, or the
+    // projection-scale bound of footprint()), so n <= D sum_k R_k and
+    // |c| <= D sum_k R_k max|rho_k| (max over view k's box); each bound is
+    // scaled to at most 2^30.  The terms are rounded, which adds at most 1/2
+    // per (ray, piece) term, and a ray meets one cell in at most 4 pieces; the
+    // host keeps the pixels of one update (>= sum_k R_k) at most 2^28, so the
+    // rounding adds at most 2^29: n stays below 2^32 and |c| below 2^31.
+    // D: a ring-sector cell of angle dtheta < pi spans at most
+    // sqrt(dr^2 + (2 r_out sin(dtheta/2))^2) across the axis (opposite corners
+    // or the outer chord), and at most 2 r_out for dtheta >= pi; r_out <= r_B.
+    const float rB = T.r[B.rB].x;
+    const float dxy = g.dtheta >= 3.14159265f
+                          ? 2.0f * rB
+                          : sqrtf(g.dr * g.dr + 4.0f * rB * rB * sinf(0.5f * g.dtheta) * sinf(0.5f * g.dtheta));
+    const float dcell = sqrtf(g.dh * g.dh + dxy * dxy) * 1.001f;
     float nscale = 1.0f, inv_nscale = 1.0f, cscale = 1.0f, inv_cscale = 1.0f;
+    const size_t npv = (size_t)g.rows * g.cols;
+    const int32_t *__restrict__ vlist = item.views;
+    // footprint of the last view of the scale pass, reused when the update has one view
+    int fu0 = 0, fu1 = -1, fv0 = 0, fv1 = -1;
     __syncthreads();
     if (live) {
-        for (int k = view_begin; k < view_end; ++k) {
-            const ViewDev &V = g.views[k];
-            int u0, u1, v0, v1;
-            if (!footprint(g, T, V, B, u0, u1, v0, v1)) continue;
-            u0 = __builtin_amdgcn_readfirstlane(u0);
-            u1 = __builtin_amdgcn_readfirstlane(u1);
-            v0 = __builtin_amdgcn_readfirstlane(v0);
-            v1 = __builtin_amdgcn_readfirstlane(v1);
-            const int nu = u1 - u0 + 1;
-            const int npix = nu * (v1 - v0 + 1);
-            if (MODE == 1) {
-                int e;
-                frexpf(1073741824.0f / (dcell * (float)npix), &e);
-                nscale = ldexpf(1.0f, e - 1);
-                inv_nscale = ldexpf(1.0f, 1 - e);
+        if (MODE == 1) {
+            float nb = 0.0f, cb = 0.0f;
+            for (int k = view_begin; k < view_end; ++k) {
+                const int view = vlist ? vlist[k] : k;
+                float rays;
+                if (!footprint(g, T, g.views[view], B, fu0, fu1, fv0, fv1, dcell, &rays)) {
+                    fu1 = -1;
+                    continue;
+                }
+                fu0 = __builtin_amdgcn_readfirstlane(fu0);
+                fu1 = __builtin_amdgcn_readfirstlane(fu1);
+                fv0 = __builtin_amdgcn_readfirstlane(fv0);
+                fv1 = __builtin_amdgcn_readfirstlane(fv1);
+                const int nu = fu1 - fu0 + 1;
+                const int npix = nu * (fv1 - fv0 + 1);
+                const float *rk = rho + (size_t)(k - view_begin) * npv;
                 float rmax = 0.0f;
                 for (int p = lane; p < npix; p += 64)
-                    rmax = fmaxf(rmax, fabsf(rho[(size_t)(v0 + p / nu) * g.cols + u0 + p % nu]));
+                    rmax = fmaxf(rmax, fabsf(rk[(size_t)(fv0 + p / nu) * g.cols + fu0 + p % nu]));
                 rmax = wave_max(rmax);
-                if (rmax > 0.0f) {
-                    frexpf(1073741824.0f / (dcell * (float)npix * rmax), &e);
+                nb += rays;
+                cb = fmaf(rays, rmax, cb);
+            }
+            if (nb > 0.0f) {
+                int e;
+                frexpf(1073741824.0f / (dcell * nb), &e);
+                nscale = ldexpf(1.0f, e - 1);
+                inv_nscale = ldexpf(1.0f, 1 - e);
+                if (cb > 0.0f) {
+                    frexpf(1073741824.0f / (dcell * cb), &e);
                     cscale = ldexpf(1.0f, e - 1);
                     inv_cscale = ldexpf(1.0f, 1 - e);
                 }
             }
+        }
+        for (int k = view_begin; k < view_end; ++k) {
+            const int view = (MODE == 1 && vlist) ? vlist[k] : k;
+            const ViewDev &V = g.views[view];
+            int u0, u1, v0, v1;
+            if (MODE == 1 && view_end - view_begin == 1) {
+                if (fu1 < fu0) continue;
+                u0 = fu0;
+                u1 = fu1;
+                v0 = fv0;
+                v1 = fv1;
+            } else {
+                if (!footprint(g, T, V, B, u0, u1, v0, v1)) continue;
+                u0 = __builtin_amdgcn_readfirstlane(u0);
+                u1 = __builtin_amdgcn_readfirstlane(u1);
+                v0 = __builtin_amdgcn_readfirstlane(v0);
+                v1 = __builtin_amdgcn_readfirstlane(v1);
+            }
+            const int nu = u1 - u0 + 1;
+            const int npix = nu * (v1 - v0 + 1);
+            const float *rk = rho + (size_t)(k - view_begin) * npv;
             for (int base = 0; base < npix; base += 64) {
                 const int p = base + lane;
                 if (p >= npix) continue;
@@ -1044,7 +1125,7 @@ __global__ __launch_bounds__(256) void bp_kernel(const BpLaunch L) {
                 const int u = u0 + p % nu;
                 float yj;
                 if (MODE == 1)
-                    yj = rho[(size_t)v * g.cols + u];
+                    yj = rk[(size_t)v * g.cols + u];
                 else
                     yj = Store<PT>::ld(y, ((size_t)k * g.rows + v) * g.cols + u);
                 if (MODE == 0 && yj == 0.0f) continue;
@@ -1135,19 +1216,18 @@ static FpItem fp_item(const cyl_geom *G, const void *vol, void *proj, int view, 
 }
 
 static BpItem bp_item(const cyl_geom *G, const void *y, int vb, int ve, void *vol, int accumulate, const void *vw,
-                      int vwt, float lam, int nonneg) {
+                      int vwt, float lam, int nonneg, const int32_t *views = nullptr) {
     const GeomDev &g = G->dev;
     BpItem it;
     it.g = G->dev;
     it.y = y;
     it.vol = vol;
     it.vw = vw;
+    it.views = views;
     it.view_begin = vb;
     it.view_end = ve;
     it.nwg = g.nbr * g.nbt * ((g.nbh + 3) / 4);
-    it.accumulate = accumulate;
-    it.vwt = vwt;
-    it.nonneg = nonneg;
+    it.flags = (accumulate ? 1 : 0) | (nonneg ? 2 : 0) | (vwt << 8);
     it.lam = lam;
     return it;
 }
@@ -1208,6 +1288,43 @@ static void launch_fp(const cyl_geom *G, const void *vol, int vt, void *proj, in
     }
 }
 
+// SART residuals of the views views[0 .. nv) (host list) of one scan, all from
+// the same volume; the residual image of views[i] goes to rho + i rows cols.
+static void launch_fp_views(const cyl_geom *G, const void *vol, int vt, void *proj, int pt, const int32_t *views,
+                            int nv, const void *pw, int pwt, float *rho, hipStream_t st) {
+    const int ns = fp_split(G->dev, nv);
+    const size_t npv = (size_t)G->rows * G->cols;
+    const cyl_geom *geoms[kMaxBatch];
+    for (int v0 = 0; v0 < nv; v0 += kMaxBatch) {
+        FpLaunch L;
+        L.n = std::min(kMaxBatch, nv - v0);
+        for (int i = 0; i < L.n; ++i) {
+            L.item[i] = fp_item(G, vol, proj, views[v0 + i], ns, pw, pwt, rho + (size_t)(v0 + i) * npv);
+            geoms[i] = G;
+        }
+        launch_fp_batch(L, geoms, vt, pt, true, st);
+    }
+}
+
+// Writes a host list of int32 into device memory through kernel arguments
+// (stream-ordered, and the host list need not outlive the call).
+struct I32Chunk {
+    int32_t v[512];
+};
+__global__ __launch_bounds__(512) void store_i32_kernel(int32_t *__restrict__ dst, int n, const I32Chunk c) {
+    const int i = threadIdx.x;
+    if (i < n) dst[i] = c.v[i];
+}
+
+static void store_i32(int32_t *dst, const int32_t *src, int n, hipStream_t st) {
+    for (int i0 = 0; i0 < n; i0 += 512) {
+        I32Chunk c;
+        const int m = std::min(512, n - i0);
+        for (int i = 0; i < m; ++i) c.v[i] = src[i0 + i];
+        hipLaunchKernelGGL(store_i32_kernel, dim3(1), dim3(512), 0, st, dst + i0, m, c);
+    }
+}
+
 template <int VT, int PT>
 static void launch_bp_t(const BpLaunch &L, const LaunchShape &sh, bool sart, hipStream_t st) {
     dim3 grid(sh.maxwg, L.n);
@@ -1245,12 +1362,14 @@ static void launch_bp_batch(const BpLaunch &L, const cyl_geom *const *geoms, int
 }
 
 // Plain BP of views [vb, ve) (one item: the views accumulate in LDS) or the
-// SART update of one view.
+// SART update of positions [vb, ve) (views[k], or view k without a list; the
+// residual image of position k at rho + (k - vb) rows cols).
 static void launch_bp(const cyl_geom *G, const void *y, int pt, int vb, int ve, void *vol, int vt, int accumulate,
-                      bool sart, const float *rho, const void *vw, int vwt, float lam, int nonneg, hipStream_t st) {
+                      bool sart, const float *rho, const void *vw, int vwt, float lam, int nonneg, hipStream_t st,
+                      const int32_t *views = nullptr) {
     BpLaunch L;
     L.n = 1;
-    L.item[0] = bp_item(G, sart ? (const void *)rho : y, vb, ve, vol, accumulate, vw, vwt, lam, nonneg);
+    L.item[0] = bp_item(G, sart ? (const void *)rho : y, vb, ve, vol, accumulate, vw, vwt, lam, nonneg, views);
     const cyl_geom *geoms[1] = {G};
     launch_bp_batch(L, geoms, vt, pt, sart, st);
 }
@@ -1350,33 +1469,40 @@ extern "C" size_t cyl_sart_workspace_bytes(const cyl_geom *G, const cyl_sart_par
     return (n + 255) & ~(size_t)255;
 }
 
-extern "C" int cyl_sart_run(const cyl_geom *G, const cyl_sart_params *P, const void *proj, cyl_dtype pt,
-                            const void *pw, cyl_dtype pwt, const void *vw, cyl_dtype vwt, void *vol,
-                            cyl_dtype vt, void *workspace, size_t ws_bytes, void *hip_stream) {
+// Checks shared by the SART sweeps; `who` names the entry point in errors.
+static int sart_check(const char *who, const cyl_geom *G, const cyl_sart_params *P, const void *proj, cyl_dtype pt,
+                      const void *pw, cyl_dtype pwt, const void *vw, cyl_dtype vwt, const void *vol, cyl_dtype vt) {
     if (!G || !P || !proj || !vol) {
-        set_error("cyl_sart_run: NULL argument");
+        set_error("%s: NULL argument", who);
         return CYL_EINVAL;
     }
     int rc;
-    if ((rc = check_dtype(vt, "cyl_sart_run volume")) || (rc = check_dtype(pt, "cyl_sart_run projections")))
-        return rc;
-    if (pw && (rc = check_dtype(pwt, "cyl_sart_run projection weights"))) return rc;
-    if (vw && (rc = check_dtype(vwt, "cyl_sart_run voxel weights"))) return rc;
+    if ((rc = check_dtype(vt, "SART volume")) || (rc = check_dtype(pt, "SART projections"))) return rc;
+    if (pw && (rc = check_dtype(pwt, "SART projection weights"))) return rc;
+    if (vw && (rc = check_dtype(vwt, "SART voxel weights"))) return rc;
     if (P->n_iter < 0 || P->start_iter < 0 || P->start_view < 0 || P->start_view > G->n_views) {
-        set_error("cyl_sart_run: invalid iteration counts (n_iter %d, start %d/%d)", P->n_iter, P->start_iter,
+        set_error("%s: invalid iteration counts (n_iter %d, start %d/%d)", who, P->n_iter, P->start_iter,
                   P->start_view);
         return CYL_EINVAL;
     }
     if (!std::isfinite(P->lambda)) {
-        set_error("cyl_sart_run: lambda must be finite");
+        set_error("%s: lambda must be finite", who);
         return CYL_EINVAL;
     }
     if (P->view_order)
         for (int i = 0; i < G->n_views; ++i)
             if (P->view_order[i] < 0 || P->view_order[i] >= G->n_views) {
-                set_error("cyl_sart_run: view_order[%d] = %d out of range", i, P->view_order[i]);
+                set_error("%s: view_order[%d] = %d out of range", who, i, P->view_order[i]);
                 return CYL_EINVAL;
             }
+    return CYL_OK;
+}
+
+extern "C" int cyl_sart_run(const cyl_geom *G, const cyl_sart_params *P, const void *proj, cyl_dtype pt,
+                            const void *pw, cyl_dtype pwt, const void *vw, cyl_dtype vwt, void *vol,
+                            cyl_dtype vt, void *workspace, size_t ws_bytes, void *hip_stream) {
+    int rc;
+    if ((rc = sart_check("cyl_sart_run", G, P, proj, pt, pw, pwt, vw, vwt, vol, vt))) return rc;
     const size_t need = cyl_sart_workspace_bytes(G, P);
     if (!workspace || ws_bytes < need) {
         set_error("cyl_sart_run: workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
@@ -1399,6 +1525,66 @@ extern "C" int cyl_sart_run(const cyl_geom *G, const cyl_sart_params *P, const v
             launch_bp(G, nullptr, CYL_F32, k, k + 1, vol, vt, 0, true, rho, vw, vwt, lam, P->nonneg, st);
         }
         if ((rc = launch_check("cyl_sart_run"))) return rc;
+    }
+    return CYL_OK;
+}
+
+// Residual images of one subset, then the view order as int32.
+static size_t os_rho_bytes(const cyl_geom *G, int m) {
+    return ((size_t)m * G->rows * G->cols * sizeof(float) + 255) & ~(size_t)255;
+}
+
+extern "C" size_t cyl_os_sart_workspace_bytes(const cyl_geom *G, int32_t subset) {
+    if (!G || subset < 1) return 0;
+    const int m = std::min(subset, G->n_views);
+    return os_rho_bytes(G, m) + (((size_t)G->n_views * sizeof(int32_t) + 255) & ~(size_t)255);
+}
+
+extern "C" int cyl_os_sart_run(const cyl_geom *G, const cyl_sart_params *P, int32_t subset, const void *proj,
+                               cyl_dtype pt, const void *pw, cyl_dtype pwt, const void *vw, cyl_dtype vwt,
+                               void *vol, cyl_dtype vt, void *workspace, size_t ws_bytes, void *hip_stream) {
+    int rc;
+    if ((rc = sart_check("cyl_os_sart_run", G, P, proj, pt, pw, pwt, vw, vwt, vol, vt))) return rc;
+    if (subset < 1) {
+        set_error("cyl_os_sart_run: subset must be >= 1 (got %d)", subset);
+        return CYL_EINVAL;
+    }
+    const int m = std::min(subset, G->n_views);
+    if ((int64_t)m * G->rows * G->cols > (1LL << 28)) {
+        set_error("cyl_os_sart_run: a subset of %d views of %d x %d pixels exceeds 2^28 rays", m, G->rows, G->cols);
+        return CYL_EINVAL;
+    }
+    if (P->start_view % m != 0 && P->start_view != G->n_views) {
+        set_error("cyl_os_sart_run: start_view %d is not at a subset boundary (subset %d)", P->start_view, m);
+        return CYL_EINVAL;
+    }
+    const size_t need = cyl_os_sart_workspace_bytes(G, subset);
+    if (!workspace || ws_bytes < need) {
+        set_error("cyl_os_sart_run: workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+        return CYL_EINVAL;
+    }
+    if (P->start_iter >= P->n_iter) return CYL_OK;
+    DeviceGuard dg(G->device);
+    if (!dg.ok) {
+        set_error("cyl_os_sart_run: cannot select device %d", G->device);
+        return CYL_EDEVICE;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    float *rho = (float *)workspace;
+    int32_t *dlist = (int32_t *)((char *)workspace + os_rho_bytes(G, m));
+    std::vector<int32_t> order(G->n_views);
+    for (int i = 0; i < G->n_views; ++i) order[i] = P->view_order ? P->view_order[i] : i;
+    store_i32(dlist, order.data(), G->n_views, st);
+    const float lam = (float)P->lambda;
+    for (int it = P->start_iter; it < P->n_iter; ++it) {
+        const int kv0 = (it == P->start_iter) ? P->start_view : 0;
+        for (int kk = kv0; kk < G->n_views; kk += m) {
+            const int cnt = std::min(m, G->n_views - kk);
+            launch_fp_views(G, vol, vt, const_cast<void *>(proj), pt, order.data() + kk, cnt, pw, pwt, rho, st);
+            launch_bp(G, nullptr, CYL_F32, kk, kk + cnt, vol, vt, 0, true, rho, vw, vwt, lam, P->nonneg, st,
+                      dlist);
+        }
+        if ((rc = launch_check("cyl_os_sart_run"))) return rc;
     }
     return CYL_OK;
 }
