@@ -234,6 +234,42 @@ def industrial_phantom(grid: Grid, seed: int, n_annuli=6, n_incl=8,
                    blocks=blocks, removed=removed, ring=ring)
 
 
+def line_phantom(grid: Grid, kind: str, n_l: int, amplitude: float = MU_PER_DENSITY):
+    """Line phantoms of the MTF study (Sec. 2.3, Fig. 3): a cosine with n_l
+    periods along theta (kind "azimuthal": every slice a Siemens star) or
+    along r over [r_min, r_max] (kind "radial": concentric circles), between
+    0 and `amplitude`, constant along h.  Values are taken at the cell
+    centres with the phase of the cell's lower edge, so that at the Nyquist
+    rate (2 cells per period) the cells alternate between 0 and the amplitude
+    (cell-centre phases would sample a cosine at its zeros there)."""
+    nh, nt, nr = grid.shape
+    if kind == "azimuthal":
+        arg = 2.0 * math.pi * n_l * np.arange(nt) / nt
+        prof = 0.5 * amplitude * (1.0 + np.cos(arg))
+        vol = np.broadcast_to(prof[None, :, None], (nh, nt, nr))
+    elif kind == "radial":
+        arg = 2.0 * math.pi * n_l * np.arange(nr) / nr
+        prof = 0.5 * amplitude * (1.0 + np.cos(arg))
+        vol = np.broadcast_to(prof[None, None, :], (nh, nt, nr))
+    else:
+        raise ValueError("kind must be 'azimuthal' or 'radial'")
+    return np.ascontiguousarray(vol, dtype=np.float64)
+
+
+def mtf_setup(n_views, n_theta=512, fine=False):
+    """Scan of the MTF study (Sec. 2.3 and 3.1): a 25 mm radius, 2.4 mm high
+    sample on (S_h, S_theta, S_r) = (32, 1608, 256) (fine=True, the phantom
+    grid) or (32, n_theta, 256) (the reconstruction grid, N_theta = 512 in the
+    paper), n_views views over a full circle on a 2048 x 128 detector of
+    0.05 mm pixels, SOD 200 mm, SDD 400 mm (the paper gives the detector
+    size only: the sample fills its width and the cone stays within its
+    height)."""
+    nt = 1608 if fine else n_theta
+    grid = Grid(32, nt, 256, 0.0, 25.0, -1.2, 1.2)
+    views = circular_views(n_views, 200.0, 400.0, 0.05)
+    return Scan(grid, views, 128, 2048, *identity_pose())
+
+
 def poisson_line_integrals(p_clean, photons, seed):
     """Noisy line integrals from Poisson counts (Sec. 2.2, Eq. 6):
     I ~ Poisson(I0 exp(-p)),  p~ = -ln(max(I, 1) / I0)."""
