@@ -316,6 +316,20 @@ int cyl_side_sums(int32_t n_views, int32_t rows, int32_t cols, const void *proj,
  * non-finite values. */
 int cyl_azimuth_phase(int32_t n, const double *s, const double *s_ref, double *alpha);
 
+/* Directional MTF of a volume (Sec. 2.3, Eq. 8) on its central h-slice: the
+ * middle slice, or the mean of the two middle slices when n_h is even, in
+ * FP64.  Each output is the modulation m = (max - min) / (max + min) (0 when
+ * max + min = 0) of a set of cells of that slice:
+ *   window = 0: out[r] over ring r (all theta), r in [0, n_r): the azimuthal
+ *               MTF at each radius;
+ *   window = w: out[k] over the rings [k w, (k + 1) w), k in [0, n_r / w):
+ *               the radial MTF in windows of one phantom period.
+ * vol: device (n_h, n_theta, n_r) of vol_type; out: device float64 array of
+ * n_r (window 0) or n_r / window entries.  Exact and order-independent.
+ * CYL_EINVAL for bad sizes, window outside [0, n_r] or NULL buffers. */
+int cyl_mtf(int32_t n_h, int32_t n_theta, int32_t n_r, const void *vol, cyl_dtype vol_type, int32_t window,
+            double *out, int32_t device, void *hip_stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *cyl_last_error(void);
 

@@ -21,7 +21,7 @@ EXPORTS = ["cyl_geom_create", "cyl_geom_destroy", "cyl_fp", "cyl_bp", "cyl_row_s
            "cyl_sart_workspace_bytes", "cyl_sart_run", "cyl_os_sart_workspace_bytes", "cyl_os_sart_run",
            "cyl_sart_residual", "cyl_sart_update",
            "cyl_sart_batch_step", "cyl_fp_diff", "cyl_add", "cyl_axis_corners", "cyl_track_point",
-           "cyl_pose_from_axis", "cyl_side_sums", "cyl_azimuth_phase", "cyl_last_error", "cyl_version"]
+           "cyl_pose_from_axis", "cyl_side_sums", "cyl_azimuth_phase", "cyl_mtf", "cyl_last_error", "cyl_version"]
 
 
 class CylError(RuntimeError):
@@ -108,6 +108,8 @@ def declare(lib):
     lib.cyl_side_sums.restype = C.c_int
     lib.cyl_azimuth_phase.argtypes = [i32, P(C.c_double), P(C.c_double), P(C.c_double)]
     lib.cyl_azimuth_phase.restype = C.c_int
+    lib.cyl_mtf.argtypes = [i32, i32, i32, vp, C.c_int, i32, vp, i32, vp]
+    lib.cyl_mtf.restype = C.c_int
     lib.cyl_last_error.argtypes = []
     lib.cyl_last_error.restype = C.c_char_p
     lib.cyl_version.argtypes = []
@@ -122,6 +124,9 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libcyl.so not found at %s: build it with "
                                "`python -m paper_2005_11976_amd.build`" % LIB_PATH)
+        # torch first: its HIP runtime must be the process's one (libcyl.so
+        # then binds to it); loaded the other way round, torch finds no GPU
+        import torch  # noqa: F401
         _lib = declare(C.CDLL(LIB_PATH))
     return _lib
 
@@ -489,6 +494,22 @@ def side_sums(proj, centre, row_lo, row_hi, stream=None, _lib=None):
                            C.c_void_p(c.data_ptr()), C.c_void_p(lo.data_ptr()), C.c_void_p(hi.data_ptr()),
                            C.c_void_p(out.data_ptr()), dev.index or 0, _stream_ptr(stream)), L)
     return out
+
+
+def mtf(vol, window=0, stream=None, _lib=None):
+    """cyl_mtf on a contiguous CUDA volume [n_h, n_theta, n_r]: modulation
+    (Eq. 8) per ring of the central slice (window 0) or per window of
+    `window` rings.  Returns a float64 CUDA tensor."""
+    import torch
+    L = _lib or lib()
+    if vol.dim() != 3 or not (vol.is_cuda and vol.is_contiguous()):
+        raise ValueError("volume must be a contiguous CUDA tensor [n_h, n_theta, n_r]")
+    nh, nt, nr = vol.shape
+    n_out = nr if window == 0 else (nr // window if 0 < window <= nr else 0)
+    out = torch.empty(max(n_out, 1), dtype=torch.float64, device=vol.device)
+    _check(L.cyl_mtf(nh, nt, nr, C.c_void_p(vol.data_ptr()), _dtype_code(vol), int(window),
+                     C.c_void_p(out.data_ptr()), vol.device.index or 0, _stream_ptr(stream)), L)
+    return out[:n_out]
 
 
 def azimuth_phase(s, s_ref, _lib=None):

@@ -234,26 +234,40 @@ def industrial_phantom(grid: Grid, seed: int, n_annuli=6, n_incl=8,
                    blocks=blocks, removed=removed, ring=ring)
 
 
-def line_phantom(grid: Grid, kind: str, n_l: int, amplitude: float = MU_PER_DENSITY):
+def line_phantom(grid: Grid, kind: str, n_l: int, amplitude: float = MU_PER_DENSITY, background: float = 0.0):
     """Line phantoms of the MTF study (Sec. 2.3, Fig. 3): a cosine with n_l
     periods along theta (kind "azimuthal": every slice a Siemens star) or
     along r over [r_min, r_max] (kind "radial": concentric circles), between
-    0 and `amplitude`, constant along h.  Values are taken at the cell
-    centres with the phase of the cell's lower edge, so that at the Nyquist
-    rate (2 cells per period) the cells alternate between 0 and the amplitude
-    (cell-centre phases would sample a cosine at its zeros there)."""
+    `background` and `background + amplitude`, constant along h.  Values are
+    taken at the cell centres with the phase of the cell's lower edge, so that
+    at the Nyquist rate (2 cells per period) the cells alternate between the
+    two extremes (cell-centre phases would sample a cosine at its zeros
+    there)."""
     nh, nt, nr = grid.shape
     if kind == "azimuthal":
         arg = 2.0 * math.pi * n_l * np.arange(nt) / nt
-        prof = 0.5 * amplitude * (1.0 + np.cos(arg))
+        prof = background + 0.5 * amplitude * (1.0 + np.cos(arg))
         vol = np.broadcast_to(prof[None, :, None], (nh, nt, nr))
     elif kind == "radial":
         arg = 2.0 * math.pi * n_l * np.arange(nr) / nr
-        prof = 0.5 * amplitude * (1.0 + np.cos(arg))
+        prof = background + 0.5 * amplitude * (1.0 + np.cos(arg))
         vol = np.broadcast_to(prof[None, None, :], (nh, nt, nr))
     else:
         raise ValueError("kind must be 'azimuthal' or 'radial'")
     return np.ascontiguousarray(vol, dtype=np.float64)
+
+
+def interleaved_order(n_views):
+    """A sweep order that visits far-apart views in turn: k_i = i s mod N with
+    the step s nearest N (1 - 1/phi) (phi the golden ratio) that is coprime
+    with N.  Consecutive SART updates then correct different directions,
+    where the sequential order spends many updates on nearly the same one."""
+    if n_views <= 2:
+        return np.arange(n_views, dtype=np.int32)
+    target = n_views * (1.0 - 2.0 / (1.0 + math.sqrt(5.0)))
+    steps = sorted(range(1, n_views), key=lambda s_: (abs(s_ - target), s_))
+    step = next(s_ for s_ in steps if math.gcd(s_, n_views) == 1)
+    return ((np.arange(n_views, dtype=np.int64) * step) % n_views).astype(np.int32)
 
 
 def mtf_setup(n_views, n_theta=512, fine=False):

@@ -66,3 +66,12 @@ def test_windows_match_loops():
     for r in range(20):
         hi, lo = max(s[:, r]), min(s[:, r])
         assert az[r] == pytest.approx((hi - lo) / (hi + lo), rel=1e-15)
+
+
+def test_interleaved_order_is_a_permutation_with_a_coprime_step():
+    for n in (1, 2, 3, 67, 120, 4096):
+        o = I.interleaved_order(n)
+        assert sorted(o.tolist()) == list(range(n))
+        if n > 2:
+            step = int(o[1])
+            assert math.gcd(step, n) == 1 and abs(step - 0.381966 * n) <= n / 10 + 1
