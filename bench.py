@@ -28,9 +28,15 @@ HBM_PEAK_GBS = 8000.0
 # device copy, taken on the kernel sources whose sha256 prefix is given here
 # (profiles/fp_bp_sart_single_256x720x128_hbm_counters.md). For any other
 # source, or another storage type, the traffic is reported as null.
-MEASURED_TRAFFIC = {"src_sha": "b5b327d6b48f4759",
-                    "fp_residual": 136111709 + 1222467,
-                    "bp_update": 341068835 + 100911102}
+MEASURED_TRAFFIC = {"src_sha": "ef92c82038a02a5c",
+                    "fp_residual": 135903134 + 1224743,
+                    "bp_update": 355631851 + 98317044}
+# VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU) of the same
+# sources (profiles/fp_bp_sart_single_256x720x128_valu_counters.md).  A wave64
+# VALU instruction takes 4 cycles of a 16-lane SIMD (packed FP32 is off), so
+# the issue capacity of a launch is 1024 SIMDs x 2.4 GHz x duration / 4.
+MEASURED_VALU = {"src_sha": "ef92c82038a02a5c", "fp_residual": 1.053e8, "bp_update": 2.814e8}
+VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
 
 
 def kernel_src_sha():
@@ -61,6 +67,9 @@ def parse():
                     help="requests in the serving measurement (0 = skip it)")
     ap.add_argument("--serve-iters", type=int, default=15)
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate, scans/s")
+    ap.add_argument("--core-only", action="store_true",
+                    help="only the SART sweep and the per-kernel timing (for profiler runs: the ordered-subset, "
+                         "pose and serving parts launch the same kernels with other shapes)")
     return ap.parse_args()
 
 
@@ -286,6 +295,11 @@ def main():
     traffic = None
     if args.dtype == "f32" and kernel_src_sha() == MEASURED_TRAFFIC["src_sha"]:
         traffic = MEASURED_TRAFFIC[dom]
+    valu = None
+    if args.dtype == "f32" and kernel_src_sha() == MEASURED_VALU["src_sha"]:
+        valu = {k: {"instructions_per_launch": MEASURED_VALU[k],
+                    "issue_frac": MEASURED_VALU[k] / (VALU_ISSUE_PER_S * ms * 1e-3)}
+                for k, ms in (("fp_residual", fp_ms), ("bp_update", bp_ms))}
     iter_bytes = scan.n_views * (fp_bytes + bp_bytes)
     path_gbs = iter_bytes * it_s / 1e9
 
@@ -298,9 +312,9 @@ def main():
         log("copy calibration: 1 GiB read + 1 GiB written")
         del src, dst
 
-    os_out = ordered_subsets(G, scan, p, prior, w, cfg["lam"], truth)
-    pose_out = pose_estimation(scan)
-    serving_out = serving(args) if args.serve_requests > 0 else None
+    os_out = None if args.core_only else ordered_subsets(G, scan, p, prior, w, cfg["lam"], truth)
+    pose_out = None if args.core_only else pose_estimation(scan)
+    serving_out = serving(args) if args.serve_requests > 0 and not args.core_only else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -332,6 +346,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "bytes_per_launch": dom_bytes},
+        "valu": valu,
         "cpu_baseline": cpu,
         "ordered_subsets": os_out,
         "serving": serving_out,
