@@ -180,6 +180,59 @@ def ordered_subsets(G, scan, p, prior, w, lam, truth):
     return out
 
 
+def comparison_projectors(G, scan, p, prior, w, lam, truth, nv=8):
+    """The paper's own pair (Sec. 2.2) beside the exact one on the same scan:
+    per-view times of the sampled FP (nearest and trilinear, step = half the
+    radial cell) and of the voxel-driven BP against the exact FP and BP, the
+    sampled projections' distance from the exact line integrals of the
+    truth, and 3 SART iterations with the pair from the prior (error against
+    the truth beside the exact pair's)."""
+    import torch
+    g = scan.grid
+    step = 0.5 * (g.r_max - g.r_min) / g.n_r
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps / nv
+
+    exact = p[:nv].float()
+    out = {"step_mm": step, "views_timed": nv}
+    buf = torch.empty_like(p)
+    out["exact_fp_ms_per_view"] = timed(lambda: G.fp(truth, buf, 0, nv))
+    for interp, name in ((0, "nearest"), (1, "linear")):
+        out["sampled_fp_%s_ms_per_view" % name] = timed(lambda: G.fp_sampled(truth, step, interp, buf, 0, nv))
+        q = buf[:nv].float()
+        out["sampled_fp_%s_rel_err_vs_exact" % name] = float((q - exact).norm() / exact.norm())
+    vol = torch.empty_like(truth)
+    out["exact_bp_ms_per_view"] = timed(lambda: G.bp(p, vol, 0, nv))
+    out["voxel_bp_ms_per_view"] = timed(lambda: G.bp_voxel(p, vol, 0, nv))
+    v = prior.clone()
+    G.sart_sampled(p, v, 1, step, 1, lam, vox_weights=w)  # warm-up
+    v.copy_(prior)
+    torch.cuda.synchronize()
+    ev[0].record()
+    G.sart_sampled(p, v, 3, step, 1, lam, vox_weights=w)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / 3
+    out["sampled_sart_linear"] = {"it_per_s": 1000.0 / ms, "iterations": 3,
+                                  "rel_err_vs_truth": float((v.float() - truth).norm() / truth.norm())}
+    log("paper's pair: sampled FP %.3f / %.3f ms per view (nearest / linear; exact %.3f), rel err vs exact "
+        "%.2e / %.2e; voxel BP %.3f ms (exact %.3f); SART %.2f it/s, err vs truth %.4f"
+        % (out["sampled_fp_nearest_ms_per_view"], out["sampled_fp_linear_ms_per_view"], out["exact_fp_ms_per_view"],
+           out["sampled_fp_nearest_rel_err_vs_exact"], out["sampled_fp_linear_rel_err_vs_exact"],
+           out["voxel_bp_ms_per_view"], out["exact_bp_ms_per_view"], out["sampled_sart_linear"]["it_per_s"],
+           out["sampled_sart_linear"]["rel_err_vs_truth"]))
+    return out
+
+
 def cpu_baseline(scan, truth, prior, weights, p, nthreads):
     """The FP64 oracle (test infrastructure) on a bounded sample: one SART
     sub-iteration (FP + residual + BP + update) for 2 of the 120 views,
@@ -313,6 +366,8 @@ def main():
         del src, dst
 
     os_out = None if args.core_only else ordered_subsets(G, scan, p, prior, w, cfg["lam"], truth)
+    cmp_out = None if args.core_only or args.dtype != "f32" else comparison_projectors(
+        G, scan, p, prior, w, cfg["lam"], truth)
     pose_out = None if args.core_only else pose_estimation(scan)
     serving_out = serving(args) if args.serve_requests > 0 and not args.core_only else None
 
@@ -349,6 +404,7 @@ def main():
         "valu": valu,
         "cpu_baseline": cpu,
         "ordered_subsets": os_out,
+        "comparison_projectors": cmp_out,
         "serving": serving_out,
         "pose_estimation": pose_out,
         "rel_err_vs_truth": rel_truth,

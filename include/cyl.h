@@ -316,6 +316,38 @@ int cyl_side_sums(int32_t n_views, int32_t rows, int32_t cols, const void *proj,
  * non-finite values. */
 int cyl_azimuth_phase(int32_t n, const double *s, const double *s_ref, double *alpha);
 
+/* The paper's own projector pair (Sec. 2.2), for comparison with the exact
+ * pair above.  Forward projection, pixel driven: each ray (source -> pixel
+ * centre) is sampled at distances (k + 1/2) step from the source; each sample
+ * inside the support goes through the cylindrical transform (Eq. 2) and adds
+ * step * mu, with mu of the cell holding it (interp = 0: t_jl = step x samples
+ * in cell l) or interpolated trilinearly between cell centres (interp = 1;
+ * theta periodic, r and h clamped to the outermost centres).  Row sums are
+ * step x (samples in the support).  FP32.  step in mm, > 0, with at most
+ * 2^30 samples across the support.  Views [view_begin, view_end) of proj
+ * ([n_views][rows][cols]) are overwritten. */
+int cyl_fp_sampled(const cyl_geom *geom, const void *vol, cyl_dtype vol_type, void *proj, cyl_dtype proj_type,
+                   int32_t view_begin, int32_t view_end, double step, int32_t interp, void *hip_stream);
+
+/* Voxel-driven back-projection (Sec. 2.2): for each cell, the bilinear reading
+ * of each view's image at the projection of the cell centre (pixels off the
+ * detector read nothing), summed over views [view_begin, view_end) of proj
+ * ([n_views][rows][cols]); vol = (accumulate ? vol : 0) + that sum.  Not the
+ * transpose of cyl_fp_sampled.  FP32. */
+int cyl_bp_voxel(const cyl_geom *geom, const void *proj, cyl_dtype proj_type, void *vol, cyl_dtype vol_type,
+                 int32_t view_begin, int32_t view_end, int32_t accumulate, void *hip_stream);
+
+/* SART (Eq. 7, one projection per update) with the paper's pair: per view k,
+ * rho = wp (p - q) / L from cyl_fp_sampled's q and row sums L, then
+ * mu_m += lambda wv_m c_m / n_m with c the voxel-driven back-projection of rho
+ * and n the bilinear weights that fell on the detector (where n > 0).
+ * Parameters, buffers and workspace (cyl_sart_workspace_bytes) as for
+ * cyl_sart_run, plus step and interp as for cyl_fp_sampled. */
+int cyl_sart_run_sampled(const cyl_geom *geom, const cyl_sart_params *params, double step, int32_t interp,
+                         const void *proj, cyl_dtype proj_type, const void *proj_weights,
+                         cyl_dtype proj_weights_type, const void *vox_weights, cyl_dtype vox_weights_type, void *vol,
+                         cyl_dtype vol_type, void *workspace, size_t workspace_bytes, void *hip_stream);
+
 /* Directional MTF of a volume (Sec. 2.3, Eq. 8) on its central h-slice: the
  * middle slice, or the mean of the two middle slices when n_h is even, in
  * FP64.  Each output is the modulation m = (max - min) / (max + min) (0 when

@@ -21,7 +21,7 @@ EXPORTS = ["cyl_geom_create", "cyl_geom_destroy", "cyl_fp", "cyl_bp", "cyl_row_s
            "cyl_sart_workspace_bytes", "cyl_sart_run", "cyl_os_sart_workspace_bytes", "cyl_os_sart_run",
            "cyl_sart_residual", "cyl_sart_update",
            "cyl_sart_batch_step", "cyl_fp_diff", "cyl_add", "cyl_axis_corners", "cyl_track_point",
-           "cyl_pose_from_axis", "cyl_side_sums", "cyl_azimuth_phase", "cyl_mtf", "cyl_last_error", "cyl_version"]
+           "cyl_pose_from_axis", "cyl_side_sums", "cyl_azimuth_phase", "cyl_mtf", "cyl_fp_sampled", "cyl_bp_voxel", "cyl_sart_run_sampled", "cyl_last_error", "cyl_version"]
 
 
 class CylError(RuntimeError):
@@ -110,6 +110,13 @@ def declare(lib):
     lib.cyl_azimuth_phase.restype = C.c_int
     lib.cyl_mtf.argtypes = [i32, i32, i32, vp, C.c_int, i32, vp, i32, vp]
     lib.cyl_mtf.restype = C.c_int
+    lib.cyl_fp_sampled.argtypes = [vp, vp, C.c_int, vp, C.c_int, i32, i32, C.c_double, i32, vp]
+    lib.cyl_fp_sampled.restype = C.c_int
+    lib.cyl_bp_voxel.argtypes = [vp, vp, C.c_int, vp, C.c_int, i32, i32, i32, vp]
+    lib.cyl_bp_voxel.restype = C.c_int
+    lib.cyl_sart_run_sampled.argtypes = [vp, P(cyl_sart_params), C.c_double, i32, vp, C.c_int, vp, C.c_int, vp,
+                                         C.c_int, vp, C.c_int, vp, C.c_size_t, vp]
+    lib.cyl_sart_run_sampled.restype = C.c_int
     lib.cyl_last_error.argtypes = []
     lib.cyl_last_error.restype = C.c_char_p
     lib.cyl_version.argtypes = []
@@ -294,6 +301,58 @@ class Geometry:
             self._vol(vox_weights)
         _check(self._L.cyl_sart_run(
             self.handle, C.byref(prm), C.c_void_p(proj.data_ptr()), _dtype_code(proj),
+            pw, _dtype_code(proj_weights) if proj_weights is not None else CYL_F32,
+            vw, _dtype_code(vox_weights) if vox_weights is not None else CYL_F32,
+            C.c_void_p(vol.data_ptr()), _dtype_code(vol), C.c_void_p(workspace.data_ptr()),
+            workspace.numel() * workspace.element_size(), _stream_ptr(stream)), self._L)
+        del keep
+        return vol
+
+    # -- the paper's own projector pair (comparison) ------------------------
+    def fp_sampled(self, vol, step, interp=0, proj=None, view_begin=0, view_end=None, out_dtype=None,
+                   stream=None):
+        """cyl_fp_sampled: equidistant samples along each ray (interp 0:
+        nearest cell, 1: trilinear)."""
+        import torch
+        view_end = self.scan.n_views if view_end is None else view_end
+        self._vol(vol)
+        if proj is None:
+            proj = torch.zeros(self.scan.proj_shape, dtype=out_dtype or vol.dtype, device=vol.device)
+        self._proj(proj)
+        _check(self._L.cyl_fp_sampled(self.handle, C.c_void_p(vol.data_ptr()), _dtype_code(vol),
+                                      C.c_void_p(proj.data_ptr()), _dtype_code(proj), view_begin, view_end,
+                                      float(step), int(interp), _stream_ptr(stream)), self._L)
+        return proj
+
+    def bp_voxel(self, proj, vol=None, view_begin=0, view_end=None, accumulate=False, out_dtype=None,
+                 stream=None):
+        """cyl_bp_voxel: voxel-driven bilinear back-projection."""
+        import torch
+        view_end = self.scan.n_views if view_end is None else view_end
+        self._proj(proj)
+        if vol is None:
+            vol = torch.zeros(self.scan.grid.shape, dtype=out_dtype or proj.dtype, device=proj.device)
+        self._vol(vol)
+        _check(self._L.cyl_bp_voxel(self.handle, C.c_void_p(proj.data_ptr()), _dtype_code(proj),
+                                    C.c_void_p(vol.data_ptr()), _dtype_code(vol), view_begin, view_end,
+                                    int(bool(accumulate)), _stream_ptr(stream)), self._L)
+        return vol
+
+    def sart_sampled(self, proj, vol, n_iter, step, interp=0, lam=0.5, proj_weights=None, vox_weights=None,
+                     nonneg=False, view_order=None, start_iter=0, start_view=0, workspace=None, stream=None):
+        """cyl_sart_run_sampled: SART with the paper's sampled FP and
+        voxel-driven BP, in place on `vol`."""
+        import torch
+        self._proj(proj)
+        self._vol(vol)
+        prm, keep = self.sart_params(n_iter, lam, nonneg, view_order, start_iter, start_view)
+        need = self.workspace_bytes(prm)
+        if workspace is None:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=vol.device)
+        pw = C.c_void_p(proj_weights.data_ptr()) if proj_weights is not None else None
+        vw = C.c_void_p(vox_weights.data_ptr()) if vox_weights is not None else None
+        _check(self._L.cyl_sart_run_sampled(
+            self.handle, C.byref(prm), float(step), int(interp), C.c_void_p(proj.data_ptr()), _dtype_code(proj),
             pw, _dtype_code(proj_weights) if proj_weights is not None else CYL_F32,
             vw, _dtype_code(vox_weights) if vox_weights is not None else CYL_F32,
             C.c_void_p(vol.data_ptr()), _dtype_code(vol), C.c_void_p(workspace.data_ptr()),
