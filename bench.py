@@ -233,6 +233,39 @@ def comparison_projectors(G, scan, p, prior, w, lam, truth, nv=8):
     return out
 
 
+def symmetric_matrix(G, scan, p, prior, w, lam, truth):
+    """The reuse of view 0's exact system matrix for every view of this
+    unposed scan (cyl_sym_*, the acceleration the posed method gives up):
+    build time, entries, device bytes, SART iterations/s over 3 iterations
+    from the prior and the distance to the truth (the same arithmetic as the
+    traversal path, summed in another order)."""
+    import torch
+    from paper_2005_11976_amd import cyl
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S = cyl.SymMatrix(G)
+    build_s = time.perf_counter() - t0
+    v = prior.clone()
+    S.sart(p, v, 1, lam, vox_weights=w)  # warm-up
+    v.copy_(prior)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    S.sart(p, v, 3, lam, vox_weights=w)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    nnz = S.nnz
+    out = {"build_s": build_s, "nnz_per_view": nnz,
+           "device_bytes": nnz * 18 + scan.grid.n_vox * 8 + scan.det_rows * scan.det_cols * 8,
+           "sart_it_per_s": 1000.0 / ms, "ms_per_view": ms / scan.n_views, "iterations": 3,
+           "rel_err_vs_truth": float((v.float() - truth).norm() / truth.norm())}
+    log("symmetric matrix: build %.2f s, %d entries, SART %.2f it/s (%.3f ms per view), err vs truth %.4f"
+        % (build_s, nnz, out["sart_it_per_s"], out["ms_per_view"], out["rel_err_vs_truth"]))
+    S.close()
+    return out
+
+
 def cpu_baseline(scan, truth, prior, weights, p, nthreads):
     """The FP64 oracle (test infrastructure) on a bounded sample: one SART
     sub-iteration (FP + residual + BP + update) for 2 of the 120 views,
@@ -368,6 +401,7 @@ def main():
     os_out = None if args.core_only else ordered_subsets(G, scan, p, prior, w, cfg["lam"], truth)
     cmp_out = None if args.core_only or args.dtype != "f32" else comparison_projectors(
         G, scan, p, prior, w, cfg["lam"], truth)
+    sym_out = None if args.core_only else symmetric_matrix(G, scan, p, prior, w, cfg["lam"], truth)
     pose_out = None if args.core_only else pose_estimation(scan)
     serving_out = serving(args) if args.serve_requests > 0 and not args.core_only else None
 
@@ -405,6 +439,7 @@ def main():
         "cpu_baseline": cpu,
         "ordered_subsets": os_out,
         "comparison_projectors": cmp_out,
+        "symmetric_matrix": sym_out,
         "serving": serving_out,
         "pose_estimation": pose_out,
         "rel_err_vs_truth": rel_truth,

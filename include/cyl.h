@@ -348,6 +348,32 @@ int cyl_sart_run_sampled(const cyl_geom *geom, const cyl_sart_params *params, do
                          cyl_dtype proj_weights_type, const void *vox_weights, cyl_dtype vox_weights_type, void *vol,
                          cyl_dtype vol_type, void *workspace, size_t workspace_bytes, void *hip_stream);
 
+/* Precomputed system matrix for scans whose views are view 0 rotated about the
+ * object axis by whole sectors (an unposed circular scan with a view step that
+ * is a multiple of 2 pi / n_theta): the reuse of the system matrix that the
+ * posed method gives up (Sec. 2).  cyl_sym_create checks the views on the host
+ * (each must match view 0 rotated by an integer number of sectors within
+ * 1e-9 of its size; CYL_EINVAL otherwise), then records view 0's exact rows
+ * t_jl with the traversal and builds its columns (device memory: 10 bytes per
+ * row entry, 8 per column entry, 8 per cell and per ray; it synchronises
+ * `hip_stream`).  The geometry must outlive the matrix.  Entries per view must
+ * stay below 2^31; n_theta <= 65535.
+ * cyl_sym_fp: q for views [view_begin, view_end) from the stored rows with the
+ *   view's theta shift (as cyl_fp computes, to rounding).
+ * cyl_sym_sart_run: weighted SART as cyl_sart_run computes it (to rounding),
+ *   from the stored rows and columns; same parameters, buffers and
+ *   workspace (cyl_sart_workspace_bytes of the geometry).  Deterministic. */
+typedef struct cyl_sym cyl_sym;
+int cyl_sym_create(const cyl_geom *geom, cyl_sym **out, void *hip_stream);
+void cyl_sym_destroy(cyl_sym *sym);
+int64_t cyl_sym_nnz(const cyl_sym *sym);
+int cyl_sym_fp(const cyl_sym *sym, const void *vol, cyl_dtype vol_type, void *proj, cyl_dtype proj_type,
+               int32_t view_begin, int32_t view_end, void *hip_stream);
+int cyl_sym_sart_run(const cyl_sym *sym, const cyl_sart_params *params, const void *proj, cyl_dtype proj_type,
+                     const void *proj_weights, cyl_dtype proj_weights_type, const void *vox_weights,
+                     cyl_dtype vox_weights_type, void *vol, cyl_dtype vol_type, void *workspace,
+                     size_t workspace_bytes, void *hip_stream);
+
 /* Directional MTF of a volume (Sec. 2.3, Eq. 8) on its central h-slice: the
  * middle slice, or the mean of the two middle slices when n_h is even, in
  * FP64.  Each output is the modulation m = (max - min) / (max + min) (0 when

@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcyl.so")
-SOURCES = ["cyl_host.cpp", "cyl_pose.cpp", "cyl_kernels.hip", "cyl_axis.hip", "cyl_mtf.hip", "cyl_sampled.hip"]
+SOURCES = ["cyl_host.cpp", "cyl_pose.cpp", "cyl_kernels.hip", "cyl_axis.hip", "cyl_mtf.hip", "cyl_sampled.hip", "cyl_sym.hip"]
 ARCH = "gfx950"
 
 

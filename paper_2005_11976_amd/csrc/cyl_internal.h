@@ -56,6 +56,10 @@ struct cyl_geom {
 };
 
 namespace cyl {
+// Records the exact pieces of every ray of one view (count pass with cells
+// null, then fill pass at rowptr offsets); see record_kernel.
+int launch_record(const cyl_geom *G, int view, const int32_t *rowptr, int32_t *counts, int32_t *cells, float *lens,
+                  float *rowsum, hipStream_t st);
 void set_error(const char *fmt, ...);
 int check_dtype(cyl_dtype t, const char *what);
 size_t dtype_size(cyl_dtype t);

@@ -691,6 +691,57 @@ __global__ __launch_bounds__(256) void fp_kernel(const FpLaunch L) {
     }
 }
 
+// Exact traversal of every ray of one view, recording its pieces inside the
+// grid (length > 0; the hole r < r_min is skipped).  Count pass (fill = 0):
+// counts[pix] = pieces and rowsum[pix] = L_j (closed form, FP64).  Fill pass:
+// the pieces of ray pix go to cells/lens from rowptr[pix], in walk order,
+// never past rowptr[pix + 1].  One kernel for both passes, so both walk with
+// the same instructions and find the same pieces.
+__global__ __launch_bounds__(256) void record_kernel(GeomDev g, int view, int fill, const int32_t *__restrict__ rowptr,
+                                                     int32_t *__restrict__ counts, int32_t *__restrict__ cells,
+                                                     float *__restrict__ lens, float *__restrict__ rowsum) {
+    extern __shared__ float2 smem[];
+    const Tabs T = stage_tables(g, smem);
+    __syncthreads();
+    const int pix = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (pix >= g.rows * g.cols) return;
+    const int u = pix % g.cols, v = pix / g.cols;
+    const ViewDev &V = g.views[view];
+    RayF r;
+    double dx, dy, dz, tc;
+    ray_geom(g, T, V, u, v, r, dx, dy, dz, tc);
+    struct Record {
+        int32_t *cells;
+        float *lens;
+        int nt, nr, n, pos, cap;
+        __device__ __forceinline__ void operator()(int h, int t, int q, float len) {
+            if (q < 0 || !(len > 0.0f)) return;
+            if (n < cap) {
+                cells[pos + n] = (h * nt + t) * nr + q;
+                lens[pos + n] = len;
+            }
+            ++n;
+        }
+        __device__ __forceinline__ void late() {}
+    } rec{cells, lens, g.n_theta, g.n_r, 0, fill ? rowptr[pix] : 0, fill ? rowptr[pix + 1] - rowptr[pix] : 0};
+    if ((r.flags & RAY_HIT) && r.s_out > r.s_in) {
+        int ih, it, ir;
+        cell_at(g, r, r.s_in, ih, it, ir);
+        const Box bx{0, g.n_h, 0, g.n_theta, -1, g.n_r + 1};
+        traverse<false>(g, T, V, r, r.s_in, r.s_out, ih, it, ir, bx, rec);
+    }
+    if (!fill) {
+        counts[pix] = rec.n;
+        rowsum[pix] = row_sum_fp64(g, V, r, dx, dy, dz, tc);
+    } else {
+        // a row the fill pass found shorter is padded with empty entries
+        for (int i = rec.n; i < rec.cap; ++i) {
+            cells[rec.pos + i] = 0;
+            lens[rec.pos + i] = 0.0f;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void rowsum_kernel(GeomDev g, float *__restrict__ out, int view_begin) {
     extern __shared__ float2 smem[];
     const Tabs T = stage_tables(g, smem);
@@ -1181,6 +1232,16 @@ static int launch_check(const char *what) {
 
 static size_t table_bytes(const GeomDev &g) {
     return sizeof(float2) * ((size_t)(g.n_r + 1) + (g.n_h + 1) + (g.n_theta + 1));
+}
+
+int launch_record(const cyl_geom *G, int view, const int32_t *rowptr, int32_t *counts, int32_t *cells, float *lens,
+                  float *rowsum, hipStream_t st) {
+    const GeomDev &g = G->dev;
+    const dim3 grid((unsigned)((g.rows * g.cols + 255) / 256));
+    const size_t lds = table_bytes(g);
+    hipLaunchKernelGGL(record_kernel, grid, dim3(256), lds, st, g, view, cells ? 1 : 0, rowptr, counts, cells, lens,
+                       rowsum);
+    return launch_check("record");
 }
 
 static size_t bp_lds_bytes(const GeomDev &g, bool sart) {

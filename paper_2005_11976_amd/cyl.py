@@ -21,7 +21,8 @@ EXPORTS = ["cyl_geom_create", "cyl_geom_destroy", "cyl_fp", "cyl_bp", "cyl_row_s
            "cyl_sart_workspace_bytes", "cyl_sart_run", "cyl_os_sart_workspace_bytes", "cyl_os_sart_run",
            "cyl_sart_residual", "cyl_sart_update",
            "cyl_sart_batch_step", "cyl_fp_diff", "cyl_add", "cyl_axis_corners", "cyl_track_point",
-           "cyl_pose_from_axis", "cyl_side_sums", "cyl_azimuth_phase", "cyl_mtf", "cyl_fp_sampled", "cyl_bp_voxel", "cyl_sart_run_sampled", "cyl_last_error", "cyl_version"]
+           "cyl_pose_from_axis", "cyl_side_sums", "cyl_azimuth_phase", "cyl_mtf", "cyl_fp_sampled", "cyl_bp_voxel", "cyl_sart_run_sampled", "cyl_sym_create", "cyl_sym_destroy", "cyl_sym_nnz",
+           "cyl_sym_fp", "cyl_sym_sart_run", "cyl_last_error", "cyl_version"]
 
 
 class CylError(RuntimeError):
@@ -117,6 +118,17 @@ def declare(lib):
     lib.cyl_sart_run_sampled.argtypes = [vp, P(cyl_sart_params), C.c_double, i32, vp, C.c_int, vp, C.c_int, vp,
                                          C.c_int, vp, C.c_int, vp, C.c_size_t, vp]
     lib.cyl_sart_run_sampled.restype = C.c_int
+    lib.cyl_sym_create.argtypes = [vp, P(vp), vp]
+    lib.cyl_sym_create.restype = C.c_int
+    lib.cyl_sym_destroy.argtypes = [vp]
+    lib.cyl_sym_destroy.restype = None
+    lib.cyl_sym_nnz.argtypes = [vp]
+    lib.cyl_sym_nnz.restype = C.c_int64
+    lib.cyl_sym_fp.argtypes = [vp, vp, C.c_int, vp, C.c_int, i32, i32, vp]
+    lib.cyl_sym_fp.restype = C.c_int
+    lib.cyl_sym_sart_run.argtypes = [vp, P(cyl_sart_params), vp, C.c_int, vp, C.c_int, vp, C.c_int, vp, C.c_int,
+                                     vp, C.c_size_t, vp]
+    lib.cyl_sym_sart_run.restype = C.c_int
     lib.cyl_last_error.argtypes = []
     lib.cyl_last_error.restype = C.c_char_p
     lib.cyl_version.argtypes = []
@@ -553,6 +565,68 @@ def side_sums(proj, centre, row_lo, row_hi, stream=None, _lib=None):
                            C.c_void_p(c.data_ptr()), C.c_void_p(lo.data_ptr()), C.c_void_p(hi.data_ptr()),
                            C.c_void_p(out.data_ptr()), dev.index or 0, _stream_ptr(stream)), L)
     return out
+
+
+class SymMatrix:
+    """cyl_sym_*: view 0's exact system matrix, reused for every view of an
+    unposed scan whose views are whole-sector rotations of view 0.  Keeps
+    its geometry alive."""
+
+    def __init__(self, geom, stream=None):
+        self.geom = geom
+        self._L = geom._L
+        h = C.c_void_p()
+        _check(self._L.cyl_sym_create(geom.handle, C.byref(h), _stream_ptr(stream)), self._L)
+        self.handle = h
+
+    @property
+    def nnz(self):
+        return int(self._L.cyl_sym_nnz(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self._L.cyl_sym_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def fp(self, vol, proj=None, view_begin=0, view_end=None, out_dtype=None, stream=None):
+        import torch
+        g = self.geom
+        view_end = g.scan.n_views if view_end is None else view_end
+        g._vol(vol)
+        if proj is None:
+            proj = torch.zeros(g.scan.proj_shape, dtype=out_dtype or vol.dtype, device=vol.device)
+        g._proj(proj)
+        _check(self._L.cyl_sym_fp(self.handle, C.c_void_p(vol.data_ptr()), _dtype_code(vol),
+                                  C.c_void_p(proj.data_ptr()), _dtype_code(proj), view_begin, view_end,
+                                  _stream_ptr(stream)), self._L)
+        return proj
+
+    def sart(self, proj, vol, n_iter, lam=0.5, proj_weights=None, vox_weights=None, nonneg=False, view_order=None,
+             start_iter=0, start_view=0, workspace=None, stream=None):
+        import torch
+        g = self.geom
+        g._proj(proj)
+        g._vol(vol)
+        prm, keep = g.sart_params(n_iter, lam, nonneg, view_order, start_iter, start_view)
+        need = g.workspace_bytes(prm)
+        if workspace is None:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=vol.device)
+        pw = C.c_void_p(proj_weights.data_ptr()) if proj_weights is not None else None
+        vw = C.c_void_p(vox_weights.data_ptr()) if vox_weights is not None else None
+        _check(self._L.cyl_sym_sart_run(
+            self.handle, C.byref(prm), C.c_void_p(proj.data_ptr()), _dtype_code(proj),
+            pw, _dtype_code(proj_weights) if proj_weights is not None else CYL_F32,
+            vw, _dtype_code(vox_weights) if vox_weights is not None else CYL_F32,
+            C.c_void_p(vol.data_ptr()), _dtype_code(vol), C.c_void_p(workspace.data_ptr()),
+            workspace.numel() * workspace.element_size(), _stream_ptr(stream)), self._L)
+        del keep
+        return vol
 
 
 def mtf(vol, window=0, stream=None, _lib=None):
