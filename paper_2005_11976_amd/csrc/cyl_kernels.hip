@@ -1026,7 +1026,7 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Vi
             }
         }
         __device__ __forceinline__ void late() {}
-    } visit{acc_c - off, acc64 - off, ps, rs, yj, nscale};
+    } visit{COLSUM ? nullptr : acc_c - off, COLSUM ? acc64 - off : nullptr, ps, rs, yj, nscale};
     const Box bx{B.hA, B.hB - B.hA, B.tA, B.tB - B.tA, B.rA, B.rB - B.rA};
     for (int piece = 0; piece < 2; ++piece) {
         const float a0 = piece ? pb0 : pa0, a1 = piece ? pb1 : pa1;
@@ -1047,32 +1047,25 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Vi
     }
 }
 
-// Workgroup of 4 waves; each wave owns one block of cells and loops over the
-// views, over the detector pixels of the block footprint, traces each ray
-// through the block hull and accumulates c_m = sum t_jm y_j and
-// n_m = sum t_jm in wave-private LDS (deterministic: no wave shares a slot).
-// MODE 0: vol = (accumulate ? vol : 0) + c.  MODE 1 (SART, the views of one
-// ordered subset, c and n summed over all their rays): vol += lam * wv * c / n
-// where n > 0.
-template <int VT, int PT, int MODE>
+// Plain transpose A^T y.  Workgroup of 4 waves; each wave owns one block of
+// cells and loops over the views, over the detector pixels of the block
+// footprint, traces each ray through the block hull and accumulates
+// c_m = sum t_jm y_j in wave-private LDS (float atomics; deterministic, as no
+// two waves share a slot).  vol = (accumulate ? vol : 0) + c.
+template <int VT, int PT>
 __global__ __launch_bounds__(256) void bp_kernel(const BpLaunch L) {
     const BpItem &item = L.item[blockIdx.y];
     if ((int)blockIdx.x >= item.nwg) return;
     const GeomDev &g = item.g;
     const void *__restrict__ y = item.y;
-    const float *__restrict__ rho = (const float *)item.y;
     void *__restrict__ vol = item.vol;
-    const void *__restrict__ vw = item.vw;
     const int view_begin = item.view_begin, view_end = item.view_end;
-    const int accumulate = item.flags & 1, nonneg = (item.flags >> 1) & 1, vwt = item.flags >> 8;
-    const float lam = item.lam;
+    const int accumulate = item.flags & 1;
     extern __shared__ float2 smem[];
     const Tabs T = stage_tables(g, smem, false);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int slots = g.bh * (g.bt * (g.br + 1) + 1) + 1;
-    // MODE 0: one float per slot; MODE 1: one 64-bit (c, n) word per slot (8-byte aligned)
-    float *acc_c = (float *)(smem + table_floats2(g, false)) + wave * slots * (MODE == 1 ? 2 : 1);
-    unsigned long long *acc64 = (unsigned long long *)acc_c;
+    float *acc_c = (float *)(smem + table_floats2(g, false)) + wave * slots;
     // dispatch order: outer rings first (their blocks carry the most work), and
     // the 4 waves of a workgroup take 4 blocks stacked in h (similar work, so
     // the workgroup's LDS is not held by one slow wave)
@@ -1087,103 +1080,27 @@ __global__ __launch_bounds__(256) void bp_kernel(const BpLaunch L) {
     const int wt = B.tB - B.tA, wr = B.rB - B.rA;
     const int ncell = (B.hB - B.hA) * wt * wr;
     const int nslot = block_slots(B);
-    for (int i = lane; i < nslot; i += 64) {
-        if (MODE == 1)
-            acc64[i] = 0ull;
-        else
-            acc_c[i] = 0.0f;
-    }
-    // fixed-point scales, common to the views of one update.  The length of a
-    // ray inside one cell is at most the cell's diameter D, and view k has at
-    // most R_k rays that meet a given cell (the footprint box's pixels, or the
-    // projection-scale bound of footprint()), so n <= D sum_k R_k and
-    // |c| <= D sum_k R_k max|rho_k| (max over view k's box); each bound is
-    // scaled to at most 2^30.  The terms are rounded, which adds at most 1/2
-    // per (ray, piece) term, and a ray meets one cell in at most 4 pieces; the
-    // host keeps the pixels of one update (>= sum_k R_k) at most 2^28, so the
-    // rounding adds at most 2^29: n stays below 2^32 and |c| below 2^31.
-    // D: a ring-sector cell of angle dtheta < pi spans at most
-    // sqrt(dr^2 + (2 r_out sin(dtheta/2))^2) across the axis (opposite corners
-    // or the outer chord), and at most 2 r_out for dtheta >= pi; r_out <= r_B.
-    const float rB = T.r[B.rB].x;
-    const float dxy = g.dtheta >= 3.14159265f
-                          ? 2.0f * rB
-                          : sqrtf(g.dr * g.dr + 4.0f * rB * rB * sinf(0.5f * g.dtheta) * sinf(0.5f * g.dtheta));
-    const float dcell = sqrtf(g.dh * g.dh + dxy * dxy) * 1.001f;
-    float nscale = 1.0f, inv_nscale = 1.0f, cscale = 1.0f, inv_cscale = 1.0f;
-    const size_t npv = (size_t)g.rows * g.cols;
-    const int32_t *__restrict__ vlist = item.views;
-    // footprint of the last view of the scale pass, reused when the update has one view
-    int fu0 = 0, fu1 = -1, fv0 = 0, fv1 = -1;
+    for (int i = lane; i < nslot; i += 64) acc_c[i] = 0.0f;
     __syncthreads();
     if (live) {
-        if (MODE == 1) {
-            float nb = 0.0f, cb = 0.0f;
-            for (int k = view_begin; k < view_end; ++k) {
-                const int view = vlist ? vlist[k] : k;
-                float rays;
-                if (!footprint(g, T, g.views[view], B, fu0, fu1, fv0, fv1, dcell, &rays)) {
-                    fu1 = -1;
-                    continue;
-                }
-                fu0 = __builtin_amdgcn_readfirstlane(fu0);
-                fu1 = __builtin_amdgcn_readfirstlane(fu1);
-                fv0 = __builtin_amdgcn_readfirstlane(fv0);
-                fv1 = __builtin_amdgcn_readfirstlane(fv1);
-                const int nu = fu1 - fu0 + 1;
-                const int npix = nu * (fv1 - fv0 + 1);
-                const float *rk = rho + (size_t)(k - view_begin) * npv;
-                float rmax = 0.0f;
-                for (int p = lane; p < npix; p += 64)
-                    rmax = fmaxf(rmax, fabsf(rk[(size_t)(fv0 + p / nu) * g.cols + fu0 + p % nu]));
-                rmax = wave_max(rmax);
-                nb += rays;
-                cb = fmaf(rays, rmax, cb);
-            }
-            if (nb > 0.0f) {
-                int e;
-                frexpf(1073741824.0f / (dcell * nb), &e);
-                nscale = ldexpf(1.0f, e - 1);
-                inv_nscale = ldexpf(1.0f, 1 - e);
-                if (cb > 0.0f) {
-                    frexpf(1073741824.0f / (dcell * cb), &e);
-                    cscale = ldexpf(1.0f, e - 1);
-                    inv_cscale = ldexpf(1.0f, 1 - e);
-                }
-            }
-        }
         for (int k = view_begin; k < view_end; ++k) {
-            const int view = (MODE == 1 && vlist) ? vlist[k] : k;
-            const ViewDev &V = g.views[view];
+            const ViewDev &V = g.views[k];
             int u0, u1, v0, v1;
-            if (MODE == 1 && view_end - view_begin == 1) {
-                if (fu1 < fu0) continue;
-                u0 = fu0;
-                u1 = fu1;
-                v0 = fv0;
-                v1 = fv1;
-            } else {
-                if (!footprint(g, T, V, B, u0, u1, v0, v1)) continue;
-                u0 = __builtin_amdgcn_readfirstlane(u0);
-                u1 = __builtin_amdgcn_readfirstlane(u1);
-                v0 = __builtin_amdgcn_readfirstlane(v0);
-                v1 = __builtin_amdgcn_readfirstlane(v1);
-            }
+            if (!footprint(g, T, V, B, u0, u1, v0, v1)) continue;
+            u0 = __builtin_amdgcn_readfirstlane(u0);
+            u1 = __builtin_amdgcn_readfirstlane(u1);
+            v0 = __builtin_amdgcn_readfirstlane(v0);
+            v1 = __builtin_amdgcn_readfirstlane(v1);
             const int nu = u1 - u0 + 1;
             const int npix = nu * (v1 - v0 + 1);
-            const float *rk = rho + (size_t)(k - view_begin) * npv;
             for (int base = 0; base < npix; base += 64) {
                 const int p = base + lane;
                 if (p >= npix) continue;
                 const int v = v0 + p / nu;
                 const int u = u0 + p % nu;
-                float yj;
-                if (MODE == 1)
-                    yj = rk[(size_t)v * g.cols + u];
-                else
-                    yj = Store<PT>::ld(y, ((size_t)k * g.rows + v) * g.cols + u);
-                if (MODE == 0 && yj == 0.0f) continue;
-                bp_ray<(MODE == 1)>(g, T, V, B, u, v, MODE == 1 ? yj * cscale : yj, acc_c, acc64, nscale);
+                const float yj = Store<PT>::ld(y, ((size_t)k * g.rows + v) * g.cols + u);
+                if (yj == 0.0f) continue;
+                bp_ray<false>(g, T, V, B, u, v, yj, acc_c, nullptr, 1.0f);
             }
         }
     }
@@ -1205,20 +1122,180 @@ __global__ __launch_bounds__(256) void bp_kernel(const BpLaunch L) {
             h += dh + c2;
         }
         const size_t gi = ((size_t)(B.hA + h) * g.n_theta + (B.tA + t)) * g.n_r + (B.rA + q);
-        const int sl = slot(B, h, t, q);
-        if (MODE == 0) {
-            const float base = accumulate ? Store<VT>::ld(vol, gi) : 0.0f;
-            Store<VT>::st(vol, gi, base + acc_c[sl]);
-        } else {
-            const unsigned long long a = acc64[sl];
-            const float n = (float)(unsigned int)a * inv_nscale;
-            if (n > 0.0f) {
-                const float c = (float)(int)(unsigned int)(a >> 32) * inv_cscale;
-                const float w = vw ? ld_any(vw, vwt, gi) : 1.0f;
-                float m = Store<VT>::ld(vol, gi) + lam * w * c / n;
-                if (nonneg && m < 0.0f) m = 0.0f;
-                Store<VT>::st(vol, gi, m);
+        const float base = accumulate ? Store<VT>::ld(vol, gi) : 0.0f;
+        Store<VT>::st(vol, gi, base + acc_c[slot(B, h, t, q)]);
+    }
+}
+
+// Super-block of the SART update: 4 blocks of the back-projection
+// decomposition merged by factors ft (theta) x fr (r) x fh (h) = 4.  Merging
+// in theta and r cuts the pixels that must be set up more than merging in h
+// (rays are nearly level): on 256x720x128, 4.3 M (ray, block) pairs per view
+// against 6.0 M for 4 blocks stacked in h and 7.1 M for single blocks.  The
+// merged wedge stays within pi (the hull clip takes it as the intersection of
+// two half-planes) or covers the whole circle.  Four blocks' slots always hold
+// the merged block's, with words to spare.
+struct SbShape {
+    int fh, ft, fr, nsh, nst, nsr;
+};
+
+__host__ __device__ __forceinline__ SbShape sb_shape(const GeomDev &g) {
+    SbShape s;
+    s.ft = (g.nbt >= 2 && 2 * g.bt <= g.n_theta / 2) ? 2 : 1;
+    s.fr = g.nbr >= 2 ? 2 : 1;
+    s.fh = 4 / (s.ft * s.fr);
+    s.nsh = (g.nbh + s.fh - 1) / s.fh;
+    s.nst = (g.nbt + s.ft - 1) / s.ft;
+    s.nsr = (g.nbr + s.fr - 1) / s.fr;
+    return s;
+}
+
+// SART update on super-blocks.  With integer (c, n) sums the order of the
+// additions does not matter, so the 4 waves of a workgroup share one
+// accumulator for a super-block, and a ray that crosses several of its
+// blocks is set up once.  The waves take batches of 64
+// footprint pixels from an LDS counter that runs across the views of the
+// update: each wave walks the views in the same order, computes the same
+// footprints and scales (same code, same inputs), and so finds the same batch
+// boundaries without synchronising.  vol += lam * wv * c / n where n > 0.
+template <int VT>
+__global__ __launch_bounds__(256) void sart_bp_kernel(const BpLaunch L) {
+    const BpItem &item = L.item[blockIdx.y];
+    if ((int)blockIdx.x >= item.nwg) return;
+    const GeomDev &g = item.g;
+    const float *__restrict__ rho = (const float *)item.y;
+    void *__restrict__ vol = item.vol;
+    const void *__restrict__ vw = item.vw;
+    const int view_begin = item.view_begin, view_end = item.view_end;
+    const int nonneg = (item.flags >> 1) & 1, vwt = item.flags >> 8;
+    const float lam = item.lam;
+    const int32_t *__restrict__ vlist = item.views;
+    extern __shared__ float2 smem[];
+    const Tabs T = stage_tables(g, smem, false);
+    const int lane = threadIdx.x & 63;
+    unsigned long long *acc64 = (unsigned long long *)(smem + table_floats2(g, false));
+    // super-block: outer rings first, as for bp_kernel
+    const SbShape sb = sb_shape(g);
+    const int per_ring = sb.nst * sb.nsh;
+    const int isr = sb.nsr - 1 - (int)blockIdx.x / per_ring;
+    const int rem = (int)blockIdx.x % per_ring;
+    const int ish = rem % sb.nsh, ist = rem / sb.nsh;
+    Block B;
+    B.hA = ish * sb.fh * g.bh;
+    B.hB = min(B.hA + sb.fh * g.bh, g.n_h);
+    B.tA = ist * sb.ft * g.bt;
+    B.tB = min(B.tA + sb.ft * g.bt, g.n_theta);
+    B.rA = isr * sb.fr * g.br;
+    B.rB = min(B.rA + sb.fr * g.br, g.n_r);
+    const int wt = B.tB - B.tA, wr = B.rB - B.rA;
+    const int ncell = (B.hB - B.hA) * wt * wr;
+    // the allocation holds 4 blocks of bh slabs plus one spare word each, so
+    // the super-block's slots leave room for the batch counter
+    const int nslot = block_slots(B);
+    unsigned int *counter = (unsigned int *)(acc64 + nslot);
+    for (int i = threadIdx.x; i < nslot; i += 256) acc64[i] = 0ull;
+    if (threadIdx.x == 0) *counter = 0u;
+    // fixed-point scales: as in bp_kernel (cell diameter D, rays per cell R_k)
+    const float rB = T.r[B.rB].x;
+    const float dxy = g.dtheta >= 3.14159265f
+                          ? 2.0f * rB
+                          : sqrtf(g.dr * g.dr + 4.0f * rB * rB * sinf(0.5f * g.dtheta) * sinf(0.5f * g.dtheta));
+    const float dcell = sqrtf(g.dh * g.dh + dxy * dxy) * 1.001f;
+    const size_t npv = (size_t)g.rows * g.cols;
+    float nb = 0.0f, cb = 0.0f;
+    for (int k = view_begin; k < view_end; ++k) {
+        const int view = vlist ? vlist[k] : k;
+        float rays;
+        int u0, u1, v0, v1;
+        if (!footprint(g, T, g.views[view], B, u0, u1, v0, v1, dcell, &rays)) continue;
+        u0 = __builtin_amdgcn_readfirstlane(u0);
+        u1 = __builtin_amdgcn_readfirstlane(u1);
+        v0 = __builtin_amdgcn_readfirstlane(v0);
+        v1 = __builtin_amdgcn_readfirstlane(v1);
+        const int nu = u1 - u0 + 1;
+        const int npix = nu * (v1 - v0 + 1);
+        const float *rk = rho + (size_t)(k - view_begin) * npv;
+        float rmax = 0.0f;
+        for (int p = lane; p < npix; p += 64)
+            rmax = fmaxf(rmax, fabsf(rk[(size_t)(v0 + p / nu) * g.cols + u0 + p % nu]));
+        rmax = wave_max(rmax);
+        nb += rays;
+        cb = fmaf(rays, rmax, cb);
+    }
+    float nscale = 1.0f, inv_nscale = 1.0f, cscale = 1.0f, inv_cscale = 1.0f;
+    if (nb > 0.0f) {
+        int e;
+        frexpf(1073741824.0f / (dcell * nb), &e);
+        nscale = ldexpf(1.0f, e - 1);
+        inv_nscale = ldexpf(1.0f, 1 - e);
+        if (cb > 0.0f) {
+            frexpf(1073741824.0f / (dcell * cb), &e);
+            cscale = ldexpf(1.0f, e - 1);
+            inv_cscale = ldexpf(1.0f, 1 - e);
+        }
+    }
+    __syncthreads();
+    // batches of 64 pixels, views in order: view k owns batch numbers
+    // [first, first + nbatch_k)
+    int k = view_begin, first = 0, nbatch = -1, u0 = 0, v0 = 0, nu = 1, npix = 0;
+    for (;;) {
+        unsigned int bi = 0;
+        if (lane == 0) bi = atomicAdd(counter, 1u);
+        const int b = (int)__builtin_amdgcn_readfirstlane(bi);
+        // advance to the view holding batch b
+        while (k < view_end && (nbatch < 0 || b >= first + nbatch)) {
+            if (nbatch >= 0) {
+                first += nbatch;
+                ++k;
+                nbatch = -1;
+                continue;
             }
+            const int view = vlist ? vlist[k] : k;
+            int uu0, uu1, vv0, vv1;
+            if (footprint(g, T, g.views[view], B, uu0, uu1, vv0, vv1)) {
+                u0 = __builtin_amdgcn_readfirstlane(uu0);
+                v0 = __builtin_amdgcn_readfirstlane(vv0);
+                nu = __builtin_amdgcn_readfirstlane(uu1) - u0 + 1;
+                npix = nu * (__builtin_amdgcn_readfirstlane(vv1) - v0 + 1);
+                nbatch = (npix + 63) / 64;
+            } else {
+                nbatch = 0;
+            }
+        }
+        if (k >= view_end) break;
+        const int p = (b - first) * 64 + lane;
+        if (p < npix) {
+            const int view = vlist ? vlist[k] : k;
+            const int v = v0 + p / nu;
+            const int u = u0 + p % nu;
+            const float yj = rho[(size_t)(k - view_begin) * npv + (size_t)v * g.cols + u];
+            bp_ray<true>(g, T, g.views[view], B, u, v, yj * cscale, nullptr, acc64, nscale);
+        }
+    }
+    __syncthreads();
+    // update: 256 lanes over the cells, i = (h wt + t) wr + q stepped by 256
+    const int dq = 256 % wr, dt = (256 / wr) % wt, dh = 256 / (wr * wt);
+    const int i0 = (int)threadIdx.x;
+    int q = i0 % wr, t = (i0 / wr) % wt, h = i0 / (wr * wt);
+    for (int i = i0; i < ncell; i += 256) {
+        if (i != i0) {
+            q += dq;
+            const int c1 = q >= wr ? 1 : 0;
+            q -= c1 ? wr : 0;
+            t += dt + c1;
+            const int c2 = t >= wt ? 1 : 0;
+            t -= c2 ? wt : 0;
+            h += dh + c2;
+        }
+        const unsigned long long a = acc64[slot(B, h, t, q)];
+        const float n = (float)(unsigned int)a * inv_nscale;
+        if (n > 0.0f) {
+            const size_t gi = ((size_t)(B.hA + h) * g.n_theta + (B.tA + t)) * g.n_r + (B.rA + q);
+            const float c = (float)(int)(unsigned int)(a >> 32) * inv_cscale;
+            const float w = vw ? ld_any(vw, vwt, gi) : 1.0f;
+            float m = Store<VT>::ld(vol, gi) + lam * w * c / n;
+            if (nonneg && m < 0.0f) m = 0.0f;
+            Store<VT>::st(vol, gi, m);
         }
     }
 }
@@ -1291,7 +1368,7 @@ static FpItem fp_item(const cyl_geom *G, const void *vol, void *proj, int view, 
 }
 
 static BpItem bp_item(const cyl_geom *G, const void *y, int vb, int ve, void *vol, int accumulate, const void *vw,
-                      int vwt, float lam, int nonneg, const int32_t *views = nullptr) {
+                      int vwt, float lam, int nonneg, bool sart, const int32_t *views = nullptr) {
     const GeomDev &g = G->dev;
     BpItem it;
     it.g = G->dev;
@@ -1301,7 +1378,12 @@ static BpItem bp_item(const cyl_geom *G, const void *y, int vb, int ve, void *vo
     it.views = views;
     it.view_begin = vb;
     it.view_end = ve;
-    it.nwg = g.nbr * g.nbt * ((g.nbh + 3) / 4);
+    if (sart) {
+        const SbShape sb = sb_shape(g);
+        it.nwg = sb.nsr * sb.nst * sb.nsh;
+    } else {
+        it.nwg = g.nbr * g.nbt * ((g.nbh + 3) / 4);
+    }
     it.flags = (accumulate ? 1 : 0) | (nonneg ? 2 : 0) | (vwt << 8);
     it.lam = lam;
     return it;
@@ -1404,9 +1486,9 @@ template <int VT, int PT>
 static void launch_bp_t(const BpLaunch &L, const LaunchShape &sh, bool sart, hipStream_t st) {
     dim3 grid(sh.maxwg, L.n);
     if (sart)
-        hipLaunchKernelGGL((bp_kernel<VT, PT, 1>), grid, dim3(256), sh.lds, st, L);
+        hipLaunchKernelGGL((sart_bp_kernel<VT>), grid, dim3(256), sh.lds, st, L);
     else
-        hipLaunchKernelGGL((bp_kernel<VT, PT, 0>), grid, dim3(256), sh.lds, st, L);
+        hipLaunchKernelGGL((bp_kernel<VT, PT>), grid, dim3(256), sh.lds, st, L);
 }
 
 template <int VT>
@@ -1444,7 +1526,7 @@ static void launch_bp(const cyl_geom *G, const void *y, int pt, int vb, int ve, 
                       const int32_t *views = nullptr) {
     BpLaunch L;
     L.n = 1;
-    L.item[0] = bp_item(G, sart ? (const void *)rho : y, vb, ve, vol, accumulate, vw, vwt, lam, nonneg, views);
+    L.item[0] = bp_item(G, sart ? (const void *)rho : y, vb, ve, vol, accumulate, vw, vwt, lam, nonneg, sart, views);
     const cyl_geom *geoms[1] = {G};
     launch_bp_batch(L, geoms, vt, pt, sart, st);
 }
@@ -1794,7 +1876,7 @@ extern "C" int cyl_sart_batch_step(int32_t n, const cyl_sart_batch_item *items, 
         for (int i = 0; i < L.n; ++i) {
             const cyl_sart_batch_item &it = items[i0 + i];
             L.item[i] = bp_item(it.geom, it.workspace, it.view, it.view + 1, it.vol, 0, it.vox_weights, vwt,
-                                (float)it.lambda, it.nonneg);
+                                (float)it.lambda, it.nonneg, true);
             geoms[i] = it.geom;
         }
         launch_bp_batch(L, geoms, vt, CYL_F32, true, st);
