@@ -28,14 +28,14 @@ HBM_PEAK_GBS = 8000.0
 # device copy, taken on the kernel sources whose sha256 prefix is given here
 # (profiles/fp_bp_sart_single_256x720x128_hbm_counters.md). For any other
 # source, or another storage type, the traffic is reported as null.
-MEASURED_TRAFFIC = {"src_sha": "ef92c82038a02a5c",
-                    "fp_residual": 135903134 + 1224743,
-                    "bp_update": 355631851 + 98317044}
+MEASURED_TRAFFIC = {"src_sha": "22141f3505e04321",
+                    "fp_residual": 129279824 + 1278009,
+                    "bp_update": 194254345 + 93193984}
 # VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU) of the same
 # sources (profiles/fp_bp_sart_single_256x720x128_valu_counters.md).  A wave64
 # VALU instruction takes 4 cycles of a 16-lane SIMD (packed FP32 is off), so
 # the issue capacity of a launch is 1024 SIMDs x 2.4 GHz x duration / 4.
-MEASURED_VALU = {"src_sha": "ef92c82038a02a5c", "fp_residual": 1.053e8, "bp_update": 2.814e8}
+MEASURED_VALU = {"src_sha": "22141f3505e04321", "fp_residual": 1.046e8, "bp_update": 2.526e8}
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
 
 
