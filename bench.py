@@ -35,7 +35,10 @@ MEASURED_TRAFFIC = {"src_sha": "22141f3505e04321",
 # sources (profiles/fp_bp_sart_single_256x720x128_valu_counters.md).  A wave64
 # VALU instruction takes 4 cycles of a 16-lane SIMD (packed FP32 is off), so
 # the issue capacity of a launch is 1024 SIMDs x 2.4 GHz x duration / 4.
-MEASURED_VALU = {"src_sha": "22141f3505e04321", "fp_residual": 1.046e8, "bp_update": 2.526e8}
+# active_lanes: SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU), the fraction of
+# the 64 lanes that work in an average VALU instruction.
+MEASURED_VALU = {"src_sha": "22141f3505e04321", "fp_residual": 1.046e8, "bp_update": 2.526e8,
+                 "active_lanes": {"fp_residual": 0.951, "bp_update": 0.699}}
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
 
 
@@ -384,7 +387,8 @@ def main():
     valu = None
     if args.dtype == "f32" and kernel_src_sha() == MEASURED_VALU["src_sha"]:
         valu = {k: {"instructions_per_launch": MEASURED_VALU[k],
-                    "issue_frac": MEASURED_VALU[k] / (VALU_ISSUE_PER_S * ms * 1e-3)}
+                    "issue_frac": MEASURED_VALU[k] / (VALU_ISSUE_PER_S * ms * 1e-3),
+                    "active_lanes": MEASURED_VALU["active_lanes"][k]}
                 for k, ms in (("fp_residual", fp_ms), ("bp_update", bp_ms))}
     iter_bytes = scan.n_views * (fp_bytes + bp_bytes)
     path_gbs = iter_bytes * it_s / 1e9
