@@ -968,8 +968,8 @@ __device__ __forceinline__ int block_slots(const Block &B) { return slot(B, B.hB
 // COLSUM = true (SART): c_m and n_m in one 64-bit fixed-point accumulator per
 // cell, acc64 = c 2^32 + n with c = sum rint(t_jm y_j cscale) and
 // n = sum rint(t_jm nscale): one integer LDS atomic per step, and integer sums
-// do not depend on their order.  The scales keep |c| and n below 2^30 (see
-// bp_kernel), so the low word never carries into the high word; ycs = y_j cscale.
+// do not depend on their order.  The scales keep |c| and n below 2^31 (see
+// sart_scales), so the low word never carries into the high word; ycs = y_j cscale.
 template <bool COLSUM>
 __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const ViewDev &V, const Block &B, int u,
                                        int v, float yj, float *acc_c, unsigned long long *acc64, float nscale) {
@@ -1150,14 +1150,68 @@ __host__ __device__ __forceinline__ SbShape sb_shape(const GeomDev &g) {
     return s;
 }
 
+// Fixed-point scales of a super-block's SART update, {nscale, 1/nscale,
+// cscale, 1/cscale}, computed by one wave.  With D the cell diameter (a bound
+// on any chord through one cell), R_k the bound on the rays of view k that
+// meet one cell (footprint) and m_k the largest |rho| in view k's footprint,
+// n_m <= D sum_k R_k and |c_m| <= D sum_k R_k m_k; the scales are the powers
+// of two that keep these bounds at or below 2^30.  Each term is rounded by at
+// most 1/2 and an update has at most 2^28 terms (the host's limit on pixels
+// per update), so the sums of one cell stay below 2^31: c fits the signed high
+// word of acc64 and n never carries out of the low word.
+__device__ float4 sart_scales(const GeomDev &g, const Tabs &T, const Block &B, const float *__restrict__ rho,
+                              const int32_t *__restrict__ vlist, int view_begin, int view_end) {
+    const int lane = threadIdx.x & 63;
+    const float rB = T.r[B.rB].x;
+    const float dxy = g.dtheta >= 3.14159265f
+                          ? 2.0f * rB
+                          : sqrtf(g.dr * g.dr + 4.0f * rB * rB * sinf(0.5f * g.dtheta) * sinf(0.5f * g.dtheta));
+    const float dcell = sqrtf(g.dh * g.dh + dxy * dxy) * 1.001f;
+    const size_t npv = (size_t)g.rows * g.cols;
+    float nb = 0.0f, cb = 0.0f;
+    for (int k = view_begin; k < view_end; ++k) {
+        const int view = vlist ? vlist[k] : k;
+        float rays;
+        int u0, u1, v0, v1;
+        if (!footprint(g, T, g.views[view], B, u0, u1, v0, v1, dcell, &rays)) continue;
+        u0 = __builtin_amdgcn_readfirstlane(u0);
+        u1 = __builtin_amdgcn_readfirstlane(u1);
+        v0 = __builtin_amdgcn_readfirstlane(v0);
+        v1 = __builtin_amdgcn_readfirstlane(v1);
+        const int nu = u1 - u0 + 1;
+        const int npix = nu * (v1 - v0 + 1);
+        const float *rk = rho + (size_t)(k - view_begin) * npv;
+        float rmax = 0.0f;
+        for (int p = lane; p < npix; p += 64)
+            rmax = fmaxf(rmax, fabsf(rk[(size_t)(v0 + p / nu) * g.cols + u0 + p % nu]));
+        rmax = wave_max(rmax);
+        nb += rays;
+        cb = fmaf(rays, rmax, cb);
+    }
+    float4 sc = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+    if (nb > 0.0f) {
+        int e;
+        frexpf(1073741824.0f / (dcell * nb), &e);
+        sc.x = ldexpf(1.0f, e - 1);
+        sc.y = ldexpf(1.0f, 1 - e);
+        if (cb > 0.0f) {
+            frexpf(1073741824.0f / (dcell * cb), &e);
+            sc.z = ldexpf(1.0f, e - 1);
+            sc.w = ldexpf(1.0f, 1 - e);
+        }
+    }
+    return sc;
+}
+
 // SART update on super-blocks.  With integer (c, n) sums the order of the
 // additions does not matter, so the 4 waves of a workgroup share one
 // accumulator for a super-block, and a ray that crosses several of its
 // blocks is set up once.  The waves take batches of 64
 // footprint pixels from an LDS counter that runs across the views of the
-// update: each wave walks the views in the same order, computes the same
-// footprints and scales (same code, same inputs), and so finds the same batch
-// boundaries without synchronising.  vol += lam * wv * c / n where n > 0.
+// update: each wave walks the views in the same order and computes the same
+// footprints (same code, same inputs), and so finds the same batch boundaries
+// without synchronising.  Wave 0 alone finds the fixed-point scales.
+// vol += lam * wv * c / n where n > 0.
 template <int VT>
 __global__ __launch_bounds__(256) void sart_bp_kernel(const BpLaunch L) {
     const BpItem &item = L.item[blockIdx.y];
@@ -1189,52 +1243,29 @@ __global__ __launch_bounds__(256) void sart_bp_kernel(const BpLaunch L) {
     B.rB = min(B.rA + sb.fr * g.br, g.n_r);
     const int wt = B.tB - B.tA, wr = B.rB - B.rA;
     const int ncell = (B.hB - B.hA) * wt * wr;
-    // the allocation holds 4 blocks of bh slabs plus one spare word each, so
-    // the super-block's slots leave room for the batch counter
+    // The allocation holds 4 blocks of bh slabs plus one spare word each:
+    // 4 bh bt br + 4 bh bt + 4 bh + 4 words, at least 3 more than the
+    // super-block's (fh bh)((ft bt)(fr br + 1) + 1) + 1 slots (fh ft fr = 4,
+    // fh ft <= 4, fh <= 4).  Word nslot holds the batch counter, the next two
+    // the fixed-point scales.
     const int nslot = block_slots(B);
     unsigned int *counter = (unsigned int *)(acc64 + nslot);
+    float *scales = (float *)(acc64 + nslot + 1);
     for (int i = threadIdx.x; i < nslot; i += 256) acc64[i] = 0ull;
     if (threadIdx.x == 0) *counter = 0u;
-    // fixed-point scales: as in bp_kernel (cell diameter D, rays per cell R_k)
-    const float rB = T.r[B.rB].x;
-    const float dxy = g.dtheta >= 3.14159265f
-                          ? 2.0f * rB
-                          : sqrtf(g.dr * g.dr + 4.0f * rB * rB * sinf(0.5f * g.dtheta) * sinf(0.5f * g.dtheta));
-    const float dcell = sqrtf(g.dh * g.dh + dxy * dxy) * 1.001f;
     const size_t npv = (size_t)g.rows * g.cols;
-    float nb = 0.0f, cb = 0.0f;
-    for (int k = view_begin; k < view_end; ++k) {
-        const int view = vlist ? vlist[k] : k;
-        float rays;
-        int u0, u1, v0, v1;
-        if (!footprint(g, T, g.views[view], B, u0, u1, v0, v1, dcell, &rays)) continue;
-        u0 = __builtin_amdgcn_readfirstlane(u0);
-        u1 = __builtin_amdgcn_readfirstlane(u1);
-        v0 = __builtin_amdgcn_readfirstlane(v0);
-        v1 = __builtin_amdgcn_readfirstlane(v1);
-        const int nu = u1 - u0 + 1;
-        const int npix = nu * (v1 - v0 + 1);
-        const float *rk = rho + (size_t)(k - view_begin) * npv;
-        float rmax = 0.0f;
-        for (int p = lane; p < npix; p += 64)
-            rmax = fmaxf(rmax, fabsf(rk[(size_t)(v0 + p / nu) * g.cols + u0 + p % nu]));
-        rmax = wave_max(rmax);
-        nb += rays;
-        cb = fmaf(rays, rmax, cb);
-    }
-    float nscale = 1.0f, inv_nscale = 1.0f, cscale = 1.0f, inv_cscale = 1.0f;
-    if (nb > 0.0f) {
-        int e;
-        frexpf(1073741824.0f / (dcell * nb), &e);
-        nscale = ldexpf(1.0f, e - 1);
-        inv_nscale = ldexpf(1.0f, 1 - e);
-        if (cb > 0.0f) {
-            frexpf(1073741824.0f / (dcell * cb), &e);
-            cscale = ldexpf(1.0f, e - 1);
-            inv_cscale = ldexpf(1.0f, 1 - e);
+    // wave 0 finds the fixed-point scales and shares them through LDS
+    if (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0) {
+        const float4 sc = sart_scales(g, T, B, rho, vlist, view_begin, view_end);
+        if (lane == 0) {
+            scales[0] = sc.x;
+            scales[1] = sc.y;
+            scales[2] = sc.z;
+            scales[3] = sc.w;
         }
     }
     __syncthreads();
+    const float nscale = scales[0], inv_nscale = scales[1], cscale = scales[2], inv_cscale = scales[3];
     // batches of 64 pixels, views in order: view k owns batch numbers
     // [first, first + nbatch_k)
     int k = view_begin, first = 0, nbatch = -1, u0 = 0, v0 = 0, nu = 1, npix = 0;
