@@ -139,7 +139,10 @@ typedef struct {
     int32_t start_iter, start_view;
 } cyl_sart_params;
 
-/* Device workspace bytes cyl_sart_run needs for this geometry. */
+/* Device workspace bytes cyl_sart_run needs for this geometry: the FP32
+ * residual image of one view ([rows][cols]), then the largest |rho| of each
+ * aligned 8x8 pixel tile of that image ([ceil(rows/8)][ceil(cols/8)] FP32,
+ * which bounds the update's fixed-point sums), rounded up to 256 bytes. */
 size_t cyl_sart_workspace_bytes(const cyl_geom *geom, const cyl_sart_params *params);
 
 /* Weighted SART from a prior (Eq. 7; weight map Sec. 2.2; prior Sec. 1, 3.3).
@@ -172,8 +175,9 @@ int cyl_sart_run(const cyl_geom *geom, const cyl_sart_params *params, const void
  *   subset     views per update, >= 1 (values above n_views act as n_views);
  *              subset x rows x cols must not exceed 2^28 rays
  *   workspace  device buffer of at least cyl_os_sart_workspace_bytes(geom,
- *              subset) bytes (one FP32 residual image per view of a group and
- *              the view order), owned by the caller, not used by anything
+ *              subset) bytes (one FP32 residual image per view of a group,
+ *              then their 8x8 tile maxima, then the view order), owned by
+ *              the caller, not used by anything
  *              else until the work completes
  * A resume point (start_view) must fall on a group boundary.  Errors:
  * CYL_EINVAL for bad arguments (nothing is launched), CYL_EDEVICE for launch
@@ -190,7 +194,8 @@ int cyl_os_sart_run(const cyl_geom *geom, const cyl_sart_params *params, int32_t
  * cyl_sart_residual(k) then cyl_sart_update(k) on one stream is exactly
  * cyl_sart_run.
  * cyl_sart_residual: rho_j = wp_j (p_j - sum_l t_jl mu_l) / L_j for the rays of
- *   view `view`, written as FP32 into `workspace` ([rows][cols]).
+ *   view `view`, written as FP32 into `workspace` ([rows][cols], then the
+ *   largest |rho| of each aligned 8x8 tile).
  * cyl_sart_update: c_m = sum_j t_jm rho_j, n_m = sum_j t_jm over that view's
  *   rays; mu_m += lambda wv_m c_m / n_m where n_m > 0 (clamped at 0 if nonneg).
  * Arguments as for cyl_sart_run; workspace of cyl_sart_workspace_bytes(). */

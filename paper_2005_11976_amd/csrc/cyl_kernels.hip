@@ -559,6 +559,24 @@ __device__ __forceinline__ void traverse(const GeomDev &g, const Tabs &T, const 
     visit.late();
 }
 
+// Minimum and maximum over the 64 lanes of a wave (all lanes active).
+__device__ __forceinline__ float wave_min(float x) {
+    for (int o = 32; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o));
+    return x;
+}
+__device__ __forceinline__ float wave_max(float x) {
+    for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o));
+    return x;
+}
+
+// Aligned 8x8 pixel tiles of a view.  The SART workspace holds, after the FP32
+// residual images of an update, one float per tile and view: the largest
+// |rho| of the tile, written by the residual FP and read by the update to
+// bound its fixed-point sums.
+__host__ __device__ __forceinline__ size_t tile_count(const GeomDev &g) {
+    return (size_t)((g.rows + 7) >> 3) * (size_t)((g.cols + 7) >> 3);
+}
+
 // ------------------------------------------------------------ launch items
 
 // One launch covers up to kMaxBatch items, each a scan (its geometry, buffers
@@ -574,6 +592,7 @@ struct FpItem {
     void *proj;           // projections: output (plain) or measured data (SART)
     const void *pw;       // SART: projection weights or null; plain: minuend or null
     float *rho;           // residual image of the view (SART)
+    float *tmax;          // SART: largest |rho| of each aligned 8x8 pixel tile of the view
     int view, ns, nwg, pwt;  // view, pieces per ray, workgroups, type of pw
 };
 struct FpLaunch {
@@ -681,17 +700,25 @@ __global__ __launch_bounds__(256) void fp_kernel(const FpLaunch L) {
         if (piece != 0) return;
         for (int p = 1; p < nsplit; ++p) acc += part[threadIdx.x + 64 * p];
     }
-    if (!live) return;
     const size_t j = ((size_t)k * g.rows + v) * g.cols + u;
     if (!SART) {
         // plain projection, or a difference from given projections (pw)
-        Store<PT>::st(proj, j, pw ? ld_any(pw, pwt, j) - acc : acc);
-    } else {
+        if (live) Store<PT>::st(proj, j, pw ? ld_any(pw, pwt, j) - acc : acc);
+        return;
+    }
+    float rj = 0.0f;
+    if (live) {
         const float L = row_sum_fp64(g, V, r, dx, dy, dz, tc);
         const float pj = Store<PT>::ld(proj, j);
         const float w = pw ? ld_any(pw, pwt, j) : 1.0f;
-        rho[(size_t)v * g.cols + u] = (L > 0.0f) ? w * (pj - acc) / L : 0.0f;
+        rj = (L > 0.0f) ? w * (pj - acc) / L : 0.0f;
+        rho[(size_t)v * g.cols + u] = rj;
     }
+    // the wave's 64 pixels are one aligned 8x8 tile: store its largest |rho|
+    // (whole waves reach this point; a tile past the last column is skipped)
+    const float tm = wave_max(fabsf(rj));
+    const int tu = ((tile % tiles_u) * tw + grp * 8) >> 3;
+    if (lane == 0 && tu * 8 < g.cols) item.tmax[(size_t)(tile / tiles_u) * ((g.cols + 7) >> 3) + tu] = tm;
 }
 
 // Exact traversal of every ray of one view, recording its pieces inside the
@@ -780,15 +807,6 @@ __device__ __forceinline__ Block block_of(const GeomDev &g, int b) {
     B.rA = ir * g.br;
     B.rB = min(B.rA + g.br, g.n_r);
     return B;
-}
-
-__device__ __forceinline__ float wave_min(float x) {
-    for (int o = 32; o > 0; o >>= 1) x = fminf(x, __shfl_xor(x, o));
-    return x;
-}
-__device__ __forceinline__ float wave_max(float x) {
-    for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o));
-    return x;
 }
 
 // Projection of one bounding point of the block's convex hull
@@ -1153,8 +1171,9 @@ __host__ __device__ __forceinline__ SbShape sb_shape(const GeomDev &g) {
 // Fixed-point scales of a super-block's SART update, {nscale, 1/nscale,
 // cscale, 1/cscale}, computed by one wave.  With D the cell diameter (a bound
 // on any chord through one cell), R_k the bound on the rays of view k that
-// meet one cell (footprint) and m_k the largest |rho| in view k's footprint,
-// n_m <= D sum_k R_k and |c_m| <= D sum_k R_k m_k; the scales are the powers
+// meet one cell (footprint) and m_k the largest |rho| over the 8x8 tiles that
+// cover view k's footprint box (the residual FP's tile maxima; at least the
+// largest |rho| of the footprint), n_m <= D sum_k R_k and |c_m| <= D sum_k R_k m_k; the scales are the powers
 // of two that keep these bounds at or below 2^30.  Each term is rounded by at
 // most 1/2 and an update has at most 2^28 terms (the host's limit on pixels
 // per update), so the sums of one cell stay below 2^31: c fits the signed high
@@ -1178,12 +1197,12 @@ __device__ float4 sart_scales(const GeomDev &g, const Tabs &T, const Block &B, c
         u1 = __builtin_amdgcn_readfirstlane(u1);
         v0 = __builtin_amdgcn_readfirstlane(v0);
         v1 = __builtin_amdgcn_readfirstlane(v1);
-        const int nu = u1 - u0 + 1;
-        const int npix = nu * (v1 - v0 + 1);
-        const float *rk = rho + (size_t)(k - view_begin) * npv;
+        // largest |rho| of the aligned 8x8 tiles that cover the box
+        const float *tk = rho + (size_t)(view_end - view_begin) * npv + (size_t)(k - view_begin) * tile_count(g);
+        const int tpu = (g.cols + 7) >> 3, tu0 = u0 >> 3, tv0 = v0 >> 3;
+        const int ntu = (u1 >> 3) - tu0 + 1, nt = ntu * ((v1 >> 3) - tv0 + 1);
         float rmax = 0.0f;
-        for (int p = lane; p < npix; p += 64)
-            rmax = fmaxf(rmax, fabsf(rk[(size_t)(v0 + p / nu) * g.cols + u0 + p % nu]));
+        for (int p = lane; p < nt; p += 64) rmax = fmaxf(rmax, tk[(size_t)(tv0 + p / ntu) * tpu + tu0 + p % ntu]);
         rmax = wave_max(rmax);
         nb += rays;
         cb = fmaf(rays, rmax, cb);
@@ -1382,7 +1401,7 @@ static int fp_split(const GeomDev &g, int nv) {
 }
 
 static FpItem fp_item(const cyl_geom *G, const void *vol, void *proj, int view, int ns, const void *pw, int pwt,
-                      float *rho) {
+                      float *rho, float *tmax = nullptr) {
     const GeomDev &g = G->dev;
     const int tw = 8 * (4 / ns);
     FpItem it;
@@ -1391,6 +1410,7 @@ static FpItem fp_item(const cyl_geom *G, const void *vol, void *proj, int view, 
     it.proj = proj;
     it.pw = pw;
     it.rho = rho;
+    it.tmax = tmax;
     it.view = view;
     it.ns = ns;
     it.nwg = ((g.cols + tw - 1) / tw) * ((g.rows + 7) / 8);
@@ -1464,12 +1484,13 @@ static void launch_fp_batch(const FpLaunch &L, const cyl_geom *const *geoms, int
 static void launch_fp(const cyl_geom *G, const void *vol, int vt, void *proj, int pt, int vb, int nv, bool sart,
                       const void *pw, int pwt, float *rho, hipStream_t st) {
     const int ns = fp_split(G->dev, nv);
+    const size_t npv = (size_t)G->rows * G->cols;
     const cyl_geom *geoms[kMaxBatch];
     for (int v0 = 0; v0 < nv; v0 += kMaxBatch) {
         FpLaunch L;
         L.n = std::min(kMaxBatch, nv - v0);
         for (int i = 0; i < L.n; ++i) {
-            L.item[i] = fp_item(G, vol, proj, vb + v0 + i, ns, pw, pwt, rho);
+            L.item[i] = fp_item(G, vol, proj, vb + v0 + i, ns, pw, pwt, rho, sart ? rho + npv : nullptr);
             geoms[i] = G;
         }
         launch_fp_batch(L, geoms, vt, pt, sart, st);
@@ -1477,7 +1498,8 @@ static void launch_fp(const cyl_geom *G, const void *vol, int vt, void *proj, in
 }
 
 // SART residuals of the views views[0 .. nv) (host list) of one scan, all from
-// the same volume; the residual image of views[i] goes to rho + i rows cols.
+// the same volume; the residual image of views[i] goes to rho + i rows cols,
+// its 8x8 tile maxima to rho + nv rows cols + i tile_count.
 static void launch_fp_views(const cyl_geom *G, const void *vol, int vt, void *proj, int pt, const int32_t *views,
                             int nv, const void *pw, int pwt, float *rho, hipStream_t st) {
     const int ns = fp_split(G->dev, nv);
@@ -1487,7 +1509,8 @@ static void launch_fp_views(const cyl_geom *G, const void *vol, int vt, void *pr
         FpLaunch L;
         L.n = std::min(kMaxBatch, nv - v0);
         for (int i = 0; i < L.n; ++i) {
-            L.item[i] = fp_item(G, vol, proj, views[v0 + i], ns, pw, pwt, rho + (size_t)(v0 + i) * npv);
+            L.item[i] = fp_item(G, vol, proj, views[v0 + i], ns, pw, pwt, rho + (size_t)(v0 + i) * npv,
+                                rho + (size_t)nv * npv + (size_t)(v0 + i) * tile_count(G->dev));
             geoms[i] = G;
         }
         launch_fp_batch(L, geoms, vt, pt, true, st);
@@ -1653,7 +1676,7 @@ extern "C" int cyl_row_sums(const cyl_geom *G, float *out, int32_t view_begin, i
 
 extern "C" size_t cyl_sart_workspace_bytes(const cyl_geom *G, const cyl_sart_params *) {
     if (!G) return 0;
-    size_t n = (size_t)G->rows * G->cols * sizeof(float);
+    size_t n = ((size_t)G->rows * G->cols + tile_count(G->dev)) * sizeof(float);
     return (n + 255) & ~(size_t)255;
 }
 
@@ -1719,7 +1742,7 @@ extern "C" int cyl_sart_run(const cyl_geom *G, const cyl_sart_params *P, const v
 
 // Residual images of one subset, then the view order as int32.
 static size_t os_rho_bytes(const cyl_geom *G, int m) {
-    return ((size_t)m * G->rows * G->cols * sizeof(float) + 255) & ~(size_t)255;
+    return ((size_t)m * ((size_t)G->rows * G->cols + tile_count(G->dev)) * sizeof(float) + 255) & ~(size_t)255;
 }
 
 extern "C" size_t cyl_os_sart_workspace_bytes(const cyl_geom *G, int32_t subset) {
@@ -1896,7 +1919,8 @@ extern "C" int cyl_sart_batch_step(int32_t n, const cyl_sart_batch_item *items, 
         for (int i = 0; i < L.n; ++i) {
             const cyl_sart_batch_item &it = items[i0 + i];
             L.item[i] = fp_item(it.geom, it.vol, const_cast<void *>(it.proj), it.view, fp_split(it.geom->dev, 1),
-                                it.proj_weights, pwt, (float *)it.workspace);
+                                it.proj_weights, pwt, (float *)it.workspace,
+                                (float *)it.workspace + (size_t)it.geom->rows * it.geom->cols);
             geoms[i] = it.geom;
         }
         launch_fp_batch(L, geoms, vt, pt, true, st);
