@@ -291,6 +291,35 @@ def test_sart_weighted_prior_posed_scaled(torch_cuda):
     assert max(errs) <= 1e-4
 
 
+@pytest.mark.parametrize("subset", [1, 2])
+def test_sart_ragged_detector(torch_cuda, subset):
+    """A posed scan on a 13 x 21 detector (neither side a multiple of the 8x8
+    residual tiles whose maxima set the update's fixed-point scales): weighted
+    SART (subset 1) and ordered subsets of 2 views against the oracle."""
+    grid = I.Grid(8, 36, 8, 0.5, 6.0, -3.0, 3.0, 0.05)
+    R, T = I.pose_from(0.4, 0.12, 1.1, [0.3, -0.2, 0.1])
+    scan = I.Scan(grid, I.circular_views(6, 40.0, 80.0, 0.7, phi0=0.2), 13, 21, R, T)
+    ph = I.industrial_phantom(grid, 4040, n_annuli=3, n_incl=3)
+    o = ref.Oracle(scan)
+    p = o.fp(ph.truth)
+    G = _geom(scan)
+    pg, wg = dev(p.astype(np.float32)), dev(ph.weights.astype(np.float32))
+    vol = dev(ph.prior.astype(np.float32))
+    mu = ph.prior.copy()
+    for it in range(2):
+        say("ragged detector subset %d iteration %d" % (subset, it))
+        if subset == 1:
+            G.sart(pg, vol, it + 1, 0.5, vox_weights=wg, start_iter=it)
+        else:
+            G.os_sart(pg, vol, it + 1, subset, 0.5, vox_weights=wg, start_iter=it)
+        mu, _ = o.sart(p.astype(np.float32).astype(np.float64), mu, it + 1, 0.5, vox_weights=ph.weights,
+                       start_iter=it, subset=subset)
+        e = rel_l2(host(vol), mu)
+        say("ragged detector subset %d iteration %d rel L2 %.2e" % (subset, it, e))
+        assert e <= 1e-4
+    assert rel_l2(mu, ph.prior) > 1e-3  # the updates are not trivial
+
+
 def test_sart_invariants_bitwise(torch_cuda):
     torch = torch_cuda
     scan = I.scaled_single(n_h=16, n_theta=48, n_r=12, n_views=8, det=40, posed_seed=2007)
