@@ -1175,9 +1175,10 @@ __host__ __device__ __forceinline__ SbShape sb_shape(const GeomDev &g) {
 // cover view k's footprint box (the residual FP's tile maxima; at least the
 // largest |rho| of the footprint), n_m <= D sum_k R_k and |c_m| <= D sum_k R_k m_k; the scales are the powers
 // of two that keep these bounds at or below 2^30.  Each term is rounded by at
-// most 1/2 and an update has at most 2^28 terms (the host's limit on pixels
-// per update), so the sums of one cell stay below 2^31: c fits the signed high
-// word of acc64 and n never carries out of the low word.
+// most 1/2, and a cell's sum has at most 2^30 terms (at most 2^28 pixels per
+// update, the host's limit, and at most 4 pieces of a ray in one cell), so
+// the sums of one cell stay below 1.5 2^30: c fits the signed high word of
+// acc64 and n never carries out of the low word.
 __device__ float4 sart_scales(const GeomDev &g, const Tabs &T, const Block &B, const float *__restrict__ rho,
                               const int32_t *__restrict__ vlist, int view_begin, int view_end) {
     const int lane = threadIdx.x & 63;
