@@ -32,65 +32,108 @@ __device__ __forceinline__ uint64_t pack(uint32_t key, uint32_t tie) { return ((
 
 __device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
 
-// One workgroup per view.  out[view] = {TL.u, TL.v, TR.u, TR.v, BL.u, BL.v,
-// BR.u, BR.v, seed count (saturated)}; corners are -1 for an empty segment.
-__global__ __launch_bounds__(256) void axis_corner_kernel(const void *__restrict__ proj, int pt, int rows, int cols,
-                                                          float threshold, int k, int32_t *__restrict__ out) {
-    const int view = blockIdx.x;
-    const size_t npix = (size_t)rows * cols;
-    const size_t base = (size_t)view * npix;
-    const uint32_t W = (uint32_t)cols, H = (uint32_t)rows;
-    uint64_t m0 = ~0ull, m1 = ~0ull, m2 = ~0ull, m3 = ~0ull;
-    uint32_t count = 0;
-    for (size_t j = threadIdx.x; j < npix; j += blockDim.x) {
-        if (!(load_any(proj, pt, base + j) > threshold)) continue;
-        ++count;
-        const int v = (int)(j / cols), u = (int)(j % cols);
+// Saturating sum of two seed counts.
+__device__ __forceinline__ uint32_t add_sat(uint32_t a, uint32_t b) { return a + b < a ? 0xffffffffu : a + b; }
+
+// Candidates of one seed pixel (u, v): the four corners of its dilation
+// window, clipped to the detector, as (key, tie) minima.
+struct Corners {
+    uint64_t m0, m1, m2, m3;
+    uint32_t count;
+    __device__ __forceinline__ void clear() {
+        m0 = m1 = m2 = m3 = ~0ull;
+        count = 0;
+    }
+    __device__ __forceinline__ void seed(int u, int v, int k, int rows, int cols) {
+        const uint32_t W = (uint32_t)cols, H = (uint32_t)rows;
         const uint32_t ulo = (uint32_t)(u - k < 0 ? 0 : u - k), uhi = (uint32_t)(u + k >= cols ? cols - 1 : u + k);
         const uint32_t vlo = (uint32_t)(v - k < 0 ? 0 : v - k), vhi = (uint32_t)(v + k >= rows ? rows - 1 : v + k);
         m0 = umin64(m0, pack(ulo + vlo, vlo));                   // min u+v, smallest v
         m1 = umin64(m1, pack(W + vlo - uhi, vlo));               // max u-v, smallest v
         m2 = umin64(m2, pack(H + ulo - vhi, H - 1 - vhi));       // min u-v, largest v
         m3 = umin64(m3, pack(W + H - uhi - vhi, H - 1 - vhi));   // max u+v, largest v
+        count = add_sat(count, 1u);
     }
-    __shared__ uint64_t red[4][256];
-    __shared__ uint32_t cnt[256];
-    red[0][threadIdx.x] = m0;
-    red[1][threadIdx.x] = m1;
-    red[2][threadIdx.x] = m2;
-    red[3][threadIdx.x] = m3;
-    cnt[threadIdx.x] = count;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = umin64(red[c][threadIdx.x], red[c][threadIdx.x + s]);
-            const uint32_t a = cnt[threadIdx.x], b = cnt[threadIdx.x + s];
-            cnt[threadIdx.x] = a + b < a ? 0xffffffffu : a + b;
+    __device__ __forceinline__ void merge(const Corners &o) {
+        m0 = umin64(m0, o.m0);
+        m1 = umin64(m1, o.m1);
+        m2 = umin64(m2, o.m2);
+        m3 = umin64(m3, o.m3);
+        count = add_sat(count, o.count);
+    }
+};
+
+__device__ __forceinline__ Corners shfl_xor(const Corners &c, int o) {
+    Corners r;
+    r.m0 = __shfl_xor(c.m0, o);
+    r.m1 = __shfl_xor(c.m1, o);
+    r.m2 = __shfl_xor(c.m2, o);
+    r.m3 = __shfl_xor(c.m3, o);
+    r.count = __shfl_xor(c.count, o);
+    return r;
+}
+
+constexpr int kCornerThreads = 1024;
+constexpr int kCornerLoads = 16;  // independent loads in flight per lane
+
+// One workgroup of 1024 lanes per view.  Lane t reads pixels t, t + 1024, ...
+// kCornerLoads at a time (independent loads in flight), following (u, v) by carries
+// instead of dividing.  out[view] = {TL.u, TL.v, TR.u, TR.v, BL.u, BL.v,
+// BR.u, BR.v, seed count (saturated)}; corners are -1 for an empty segment.
+template <int PT>
+__global__ __launch_bounds__(kCornerThreads) void axis_corner_kernel(const void *__restrict__ proj, int rows, int cols,
+                                                                     float threshold, int k, int32_t *__restrict__ out) {
+    const int view = blockIdx.x;
+    const size_t npix = (size_t)rows * cols;
+    const size_t base = (size_t)view * npix;
+    const uint32_t W = (uint32_t)cols, H = (uint32_t)rows;
+    const int du = kCornerThreads % cols, dv = kCornerThreads / cols;
+    int u = (int)threadIdx.x % cols, v = (int)threadIdx.x / cols;
+    Corners c;
+    c.clear();
+    for (size_t j = threadIdx.x; j < npix; j += (size_t)kCornerLoads * kCornerThreads) {
+        float val[kCornerLoads];
+#pragma unroll
+        for (int q = 0; q < kCornerLoads; ++q) {
+            const size_t jq = j + (size_t)q * kCornerThreads;
+            val[q] = jq < npix ? load_any(proj, PT, base + jq) : threshold;
         }
-        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kCornerLoads; ++q) {
+            if (val[q] > threshold) c.seed(u, v, k, rows, cols);
+            u += du;
+            const int cy = u >= cols ? 1 : 0;
+            u -= cy ? cols : 0;
+            v += dv + cy;
+        }
     }
+    for (int o = 32; o > 0; o >>= 1) c.merge(shfl_xor(c, o));
+    __shared__ Corners part[kCornerThreads / 64];
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) part[wave] = c;
+    __syncthreads();
     if (threadIdx.x != 0) return;
+    for (int w = 1; w < kCornerThreads / 64; ++w) c.merge(part[w]);
     int32_t *o = out + (size_t)view * 9;
-    const uint32_t n = cnt[0];
+    const uint32_t n = c.count;
     o[8] = (int32_t)(n > 0x7fffffffu ? 0x7fffffffu : n);
     if (n == 0) {
-        for (int c = 0; c < 8; ++c) o[c] = -1;
+        for (int q = 0; q < 8; ++q) o[q] = -1;
         return;
     }
-    const uint64_t r0 = red[0][0], r1 = red[1][0], r2 = red[2][0], r3 = red[3][0];
-    uint32_t v;
-    v = (uint32_t)r0;
-    o[0] = (int32_t)((uint32_t)(r0 >> 32) - v);
-    o[1] = (int32_t)v;
-    v = (uint32_t)r1;
-    o[2] = (int32_t)(W + v - (uint32_t)(r1 >> 32));
-    o[3] = (int32_t)v;
-    v = H - 1 - (uint32_t)r2;
-    o[4] = (int32_t)((uint32_t)(r2 >> 32) + v - H);
-    o[5] = (int32_t)v;
-    v = H - 1 - (uint32_t)r3;
-    o[6] = (int32_t)(W + H - (uint32_t)(r3 >> 32) - v);
-    o[7] = (int32_t)v;
+    uint32_t t;
+    t = (uint32_t)c.m0;
+    o[0] = (int32_t)((uint32_t)(c.m0 >> 32) - t);
+    o[1] = (int32_t)t;
+    t = (uint32_t)c.m1;
+    o[2] = (int32_t)(W + t - (uint32_t)(c.m1 >> 32));
+    o[3] = (int32_t)t;
+    t = H - 1 - (uint32_t)c.m2;
+    o[4] = (int32_t)((uint32_t)(c.m2 >> 32) + t - H);
+    o[5] = (int32_t)t;
+    t = H - 1 - (uint32_t)c.m3;
+    o[6] = (int32_t)(W + H - (uint32_t)(c.m3 >> 32) - t);
+    o[7] = (int32_t)t;
 }
 
 // Per view: grey values left and right of the detector position centre[view]
@@ -189,8 +232,16 @@ extern "C" int cyl_axis_corners(int32_t n_views, int32_t rows, int32_t cols, con
         set_error("cyl_axis_corners: cannot select device %d", device);
         return CYL_EDEVICE;
     }
-    hipLaunchKernelGGL(axis_corner_kernel, dim3(n_views), dim3(256), 0, (hipStream_t)hip_stream, proj,
-                       (int)proj_type, rows, cols, (float)threshold, dilate, corners);
+    const hipStream_t st = (hipStream_t)hip_stream;
+    if (proj_type == CYL_F32)
+        hipLaunchKernelGGL(axis_corner_kernel<CYL_F32>, dim3(n_views), dim3(kCornerThreads), 0, st, proj, rows, cols,
+                           (float)threshold, dilate, corners);
+    else if (proj_type == CYL_F16)
+        hipLaunchKernelGGL(axis_corner_kernel<CYL_F16>, dim3(n_views), dim3(kCornerThreads), 0, st, proj, rows, cols,
+                           (float)threshold, dilate, corners);
+    else
+        hipLaunchKernelGGL(axis_corner_kernel<CYL_BF16>, dim3(n_views), dim3(kCornerThreads), 0, st, proj, rows, cols,
+                           (float)threshold, dilate, corners);
     hipError_t e = hipGetLastError();
     if (prev >= 0 && prev != device) hipSetDevice(prev);
     if (e != hipSuccess) {

@@ -61,6 +61,24 @@ def test_axis_corners_match_reference(torch_cuda, dtype_name):
             assert got[i, 8] == int((hi[i] > thr).sum())
 
 
+@pytest.mark.parametrize("rows,cols", [(7, 1500), (33, 512), (1, 1), (3, 1025), (65, 17)])
+def test_axis_corners_detector_shapes(torch_cuda, rows, cols):
+    """Random images on detectors wider than the kernel's 1024 lanes, exactly
+    dividing them, a single pixel, and odd shapes: corners and seed counts
+    equal the reference's."""
+    torch = torch_cuda
+    from paper_2005_11976_amd import cyl
+    rng = np.random.default_rng(4310 + rows * 7 + cols)
+    imgs = rng.uniform(0.0, 1.0, size=(3, rows, cols)).astype(np.float32)
+    imgs[1] = 0.0  # an empty view
+    say("axis corners shape", rows, cols)
+    for thr, k in ((float(np.float32(0.97)), 2), (0.5, 0)):
+        got = host(cyl.axis_corners(dev(imgs), thr, k)).astype(np.int64)
+        for i in range(3):
+            assert list(got[i, :8]) == _oracle_corners(imgs[i], thr, k), (rows, cols, thr, k, i)
+            assert got[i, 8] == int((imgs[i] > np.float32(thr)).sum())
+
+
 def test_pose_chain_against_reference_and_truth(torch_cuda):
     torch = torch_cuda
     from paper_2005_11976_amd import cyl
