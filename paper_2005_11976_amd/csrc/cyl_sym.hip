@@ -181,10 +181,27 @@ __global__ __launch_bounds__(256) void sym_update_kernel(const int32_t *__restri
     const int32_t m0 = shifted((int32_t)m, s_back, nt, nr);
     const float n = colsum[m0];
     if (!(n > 0.0f)) return;
-    float c = 0.0f;
-    for (int32_t i = colptr[m0]; i < colptr[m0 + 1]; ++i) c = fmaf(clen[i], rho[cray[i]], c);
     const float w = vw ? ld_val(vw, vwt, m) : 1.0f;
-    float mu = ld_val(vol, vt, m) + lam * w * c / n;
+    const float mu0 = ld_val(vol, vt, m);
+    // the column's entries in order, eight loaded at a time (rays and lengths,
+    // then the residual gathers) so their latencies overlap
+    const int32_t b = colptr[m0], e = colptr[m0 + 1];
+    float c = 0.0f;
+    for (int32_t i0 = b; i0 < e; i0 += 8) {
+        int32_t ray[8];
+        float len[8], y[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            ray[q] = i0 + q < e ? cray[i0 + q] : 0;
+            len[q] = i0 + q < e ? clen[i0 + q] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) y[q] = i0 + q < e ? rho[ray[q]] : 0.0f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (i0 + q < e) c = fmaf(len[q], y[q], c);
+    }
+    float mu = mu0 + lam * w * c / n;
     if (nonneg && mu < 0.0f) mu = 0.0f;
     st_val(vol, vt, m, mu);
 }
