@@ -95,8 +95,8 @@ __device__ bool sample_range(const GeomDev &g, const double *a, const double *e,
 // One thread per pixel of views [view_begin, view_begin + gridDim.y).
 // SART = false: proj[view] = q.  SART = true: rho[pixel] = wp (p - q) / L
 // (0 where L = 0) for one view (gridDim.y = 1), p read from proj.
-template <bool LINEAR, bool SART>
-__global__ __launch_bounds__(256) void fp_sampled_kernel(const GeomDev g, const void *__restrict__ vol, int vt,
+template <bool LINEAR, bool SART, int VT>
+__global__ __launch_bounds__(256) void fp_sampled_kernel(const GeomDev g, const void *__restrict__ vol,
                                                          void *__restrict__ proj, int pt, const void *__restrict__ pw,
                                                          int pwt, float *__restrict__ rho, int view_begin,
                                                          double step) {
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void fp_sampled_kernel(const GeomDev g, const 
                 const int ir = clampi((int)floorf((r - g.r_min) * g.inv_dr), 0, g.n_r - 1);
                 const int ih = clampi((int)floorf((z - g.h_min) * g.inv_dh), 0, g.n_h - 1);
                 const int it = clampi((int)floorf(th * g.inv_dtheta), 0, g.n_theta - 1);
-                q += ld_val(vol, vt, ((size_t)ih * g.n_theta + it) * g.n_r + ir);
+                q += ld_val(vol, VT, ((size_t)ih * g.n_theta + it) * g.n_r + ir);
             } else {
                 const float fr = (r - g.r_min) * g.inv_dr - 0.5f;
                 const float fh = (z - g.h_min) * g.inv_dh - 0.5f;
@@ -144,12 +144,14 @@ __global__ __launch_bounds__(256) void fp_sampled_kernel(const GeomDev g, const 
                     const int ih = clampi(h0 + dh, 0, g.n_h - 1);
                     const float whh = dh ? wh : 1.0f - wh;
                     for (int dt = 0; dt < 2; ++dt) {
-                        int it = (t0 + dt) % g.n_theta;
+                        // t0 lies in [-1, n_theta - 1]: wrap by one period either way
+                        int it = t0 + dt;
                         it += it < 0 ? g.n_theta : 0;
+                        it -= it >= g.n_theta ? g.n_theta : 0;
                         const float wtt = dt ? wt : 1.0f - wt;
                         const size_t rowb = ((size_t)ih * g.n_theta + it) * g.n_r;
-                        const float a0 = ld_val(vol, vt, rowb + clampi(r0, 0, g.n_r - 1));
-                        const float a1 = ld_val(vol, vt, rowb + clampi(r0 + 1, 0, g.n_r - 1));
+                        const float a0 = ld_val(vol, VT, rowb + clampi(r0, 0, g.n_r - 1));
+                        const float a1 = ld_val(vol, VT, rowb + clampi(r0 + 1, 0, g.n_r - 1));
                         acc = fmaf(whh * wtt, fmaf(wr, a1 - a0, a0), acc);
                     }
                 }
@@ -245,27 +247,38 @@ struct Guard {
     }
 };
 
-void launch_fp_sampled(const cyl_geom *G, const void *vol, int vt, void *proj, int pt, int vb, int nv, double step,
-                       int interp, bool sart, const void *pw, int pwt, float *rho, hipStream_t st) {
+template <int VT>
+void launch_fp_sampled_t(const cyl_geom *G, const void *vol, void *proj, int pt, int vb, int nv, double step,
+                         int interp, bool sart, const void *pw, int pwt, float *rho, hipStream_t st) {
     const int npix = G->rows * G->cols;
     for (int v0 = 0; v0 < nv; v0 += 65535) {
         const dim3 grid((npix + 255) / 256, std::min(65535, nv - v0));
+#define CYL_FP_SAMPLED(LIN, SRT)                                                                               \
+    hipLaunchKernelGGL((fp_sampled_kernel<LIN, SRT, VT>), grid, dim3(256), 0, st, G->dev, vol, proj, pt, pw, pwt, \
+                       rho, vb + v0, step)
         if (interp) {
             if (sart)
-                hipLaunchKernelGGL((fp_sampled_kernel<true, true>), grid, dim3(256), 0, st, G->dev, vol, vt, proj, pt,
-                                   pw, pwt, rho, vb + v0, step);
+                CYL_FP_SAMPLED(true, true);
             else
-                hipLaunchKernelGGL((fp_sampled_kernel<true, false>), grid, dim3(256), 0, st, G->dev, vol, vt, proj,
-                                   pt, pw, pwt, rho, vb + v0, step);
+                CYL_FP_SAMPLED(true, false);
         } else {
             if (sart)
-                hipLaunchKernelGGL((fp_sampled_kernel<false, true>), grid, dim3(256), 0, st, G->dev, vol, vt, proj,
-                                   pt, pw, pwt, rho, vb + v0, step);
+                CYL_FP_SAMPLED(false, true);
             else
-                hipLaunchKernelGGL((fp_sampled_kernel<false, false>), grid, dim3(256), 0, st, G->dev, vol, vt, proj,
-                                   pt, pw, pwt, rho, vb + v0, step);
+                CYL_FP_SAMPLED(false, false);
         }
+#undef CYL_FP_SAMPLED
     }
+}
+
+void launch_fp_sampled(const cyl_geom *G, const void *vol, int vt, void *proj, int pt, int vb, int nv, double step,
+                       int interp, bool sart, const void *pw, int pwt, float *rho, hipStream_t st) {
+    if (vt == CYL_F32)
+        launch_fp_sampled_t<CYL_F32>(G, vol, proj, pt, vb, nv, step, interp, sart, pw, pwt, rho, st);
+    else if (vt == CYL_F16)
+        launch_fp_sampled_t<CYL_F16>(G, vol, proj, pt, vb, nv, step, interp, sart, pw, pwt, rho, st);
+    else
+        launch_fp_sampled_t<CYL_BF16>(G, vol, proj, pt, vb, nv, step, interp, sart, pw, pwt, rho, st);
 }
 
 int sampled_step_check(const cyl_geom *G, double step, int interp, const char *who) {
