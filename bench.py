@@ -109,6 +109,71 @@ def serving(args):
             "rel_err_vs_per_scan_fp32": {"max": max(errs), "mean": float(np.mean(errs))}}
 
 
+def projector_rates(G, scan, truth, p):
+    """FP-only and BP-only rates: cyl_fp and cyl_bp over all views of the scan
+    (one call each; HIP-event time, median of 3 after a warm-up), as Grays/s
+    (each detector pixel of each view counts once)."""
+    import torch
+    proj = torch.empty_like(p)
+    vol = torch.empty_like(truth)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+    fp_ms = timed(lambda: G.fp(truth, proj))
+    bp_ms = timed(lambda: G.bp(p, vol))
+    rays = scan.n_views * scan.det_rows * scan.det_cols
+    log("projectors over %d views: fp %.2f ms (%.2f Grays/s), bp %.2f ms (%.2f Grays/s)"
+        % (scan.n_views, fp_ms, rays / fp_ms / 1e6, bp_ms, rays / bp_ms / 1e6))
+    return {"views": scan.n_views, "fp_ms": fp_ms, "fp_grays_per_s": rays / fp_ms / 1e6,
+            "bp_ms": bp_ms, "bp_grays_per_s": rays / bp_ms / 1e6}
+
+
+def posed_large():
+    """Weighted SART from the prior on the 512x1440x256 posed scan (60 views of
+    1024 x 768, seeded pose, Poisson data at 1e4 photons): one warm-up and two
+    timed iterations (HIP events), with the error against the truth."""
+    import torch
+    from paper_2005_11976_amd import cyl, inputs as I
+    cfg = I.config_posed()
+    scan = cfg["scan"]
+    log("posed large: phantom and data", scan.grid.shape, scan.proj_shape)
+    ph = I.industrial_phantom(scan.grid, cfg["seed"])
+    G = cyl.Geometry(scan, 0)
+    truth = torch.from_numpy(ph.truth.astype(np.float32)).cuda()
+    clean = G.fp(truth).cpu().numpy()
+    p = torch.from_numpy(I.poisson_line_integrals(clean, cfg["photons"], cfg["noise_seed"]).astype(np.float32)).cuda()
+    prior = torch.from_numpy(ph.prior.astype(np.float32)).cuda()
+    w = torch.from_numpy(ph.weights.astype(np.float32)).cuda()
+    ws = torch.empty(G.workspace_bytes(), dtype=torch.uint8, device="cuda")
+    vol = prior.clone()
+    G.sart(p, vol, 1, cfg["lam"], vox_weights=w, workspace=ws)
+    torch.cuda.synchronize()
+    n = 2
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    G.sart(p, vol, 1 + n, cfg["lam"], vox_weights=w, workspace=ws, start_iter=1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n
+    err = float((vol - truth).norm() / truth.norm())
+    G.close()
+    log("posed large: %.3f SART it/s (%.2f ms per view), error vs truth %.4f after %d iterations"
+        % (1000.0 / ms, ms / scan.n_views, err, 1 + n))
+    return {"workload": cfg["name"], "grid": list(scan.grid.shape), "views": scan.n_views,
+            "detector": [scan.det_rows, scan.det_cols], "it_per_s": 1000.0 / ms, "ms_per_view": ms / scan.n_views,
+            "iterations_timed": n, "rel_err_vs_truth": err, "data": "synthetic, Poisson at 1e4 photons"}
+
+
 def pose_estimation(scan):
     """Sec. 2.1 on the 256x720x128 scan geometry: a solid cylinder (r <= 20 mm,
     |h| <= 20 mm: one symmetric feature, as the paper segments) posed with a
@@ -409,6 +474,8 @@ def main():
         G, scan, p, prior, w, cfg["lam"], truth)
     sym_out = None if args.core_only else symmetric_matrix(G, scan, p, prior, w, cfg["lam"], truth)
     pose_out = None if args.core_only else pose_estimation(scan)
+    rates_out = None if args.core_only or args.dtype != "f32" else projector_rates(G, scan, truth, p32)
+    large_out = None if args.core_only or args.dtype != "f32" else posed_large()
     serving_out = serving(args) if args.serve_requests > 0 and not args.core_only else None
 
     cpu = None
@@ -447,6 +514,8 @@ def main():
         "comparison_projectors": cmp_out,
         "symmetric_matrix": sym_out,
         "serving": serving_out,
+        "projector_rates": rates_out,
+        "posed_large": large_out,
         "pose_estimation": pose_out,
         "rel_err_vs_truth": rel_truth,
     }
