@@ -338,11 +338,11 @@ def symmetric_matrix(G, scan, p, prior, w, lam, truth):
 
 def cpu_baseline(scan, truth, prior, weights, p, nthreads):
     """The FP64 oracle (test infrastructure) on a bounded sample: one SART
-    sub-iteration (FP + residual + BP + update) for 2 of the 120 views,
-    scaled to SART iterations/s."""
+    sub-iteration (FP + residual + BP + update) for 6 of the 120 views (about
+    13 s on 16 host threads), scaled to SART iterations/s."""
     from oracle import ref
     o = ref.Oracle(scan)
-    sample_views = [0, 60]
+    sample_views = [0, 20, 40, 60, 80, 100]
     t0 = time.perf_counter()
     P = scan.det_rows * scan.det_cols
     mu = prior.astype(np.float64).ravel().copy()
