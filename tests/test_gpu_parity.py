@@ -105,6 +105,33 @@ def test_fp_bp_edge_grids(torch_cuda, case):
     _fp_bp_check(torch_cuda, scan, 0, scan.n_views, 4011, name)
 
 
+@pytest.mark.parametrize("case", EDGE, ids=[c[0] for c in EDGE])
+def test_sart_edge_grids(torch_cuda, case):
+    """Weighted SART from a random prior on the edge grids (one, two and three
+    sectors, one cell, a hollow grid, ragged blocks, rays through the axis, a
+    25 degree tilt): the super-block update on degenerate shapes against the
+    oracle, 2 iterations."""
+    name, scan = case
+    rng = np.random.default_rng(4050)
+    truth = rng.uniform(0.0, 1.0, size=scan.grid.shape)
+    prior = truth * rng.uniform(0.8, 1.2, size=scan.grid.shape)
+    wv = rng.uniform(0.25, 1.0, size=scan.grid.shape)
+    o = ref.Oracle(scan)
+    p = o.fp(truth)
+    G = _geom(scan)
+    pg, wg = dev(p.astype(np.float32)), dev(wv.astype(np.float32))
+    vol = dev(prior.astype(np.float32))
+    mu = prior.astype(np.float32).astype(np.float64)
+    for it in range(2):
+        say(name, "sart iteration", it)
+        G.sart(pg, vol, it + 1, 0.5, vox_weights=wg, start_iter=it)
+        mu, _ = o.sart(p.astype(np.float32).astype(np.float64), mu, it + 1, 0.5, vox_weights=wv.astype(np.float32),
+                       start_iter=it)
+        e = rel_l2(host(vol), mu)
+        say(name, "sart iteration %d rel L2 %.2e" % (it, e))
+        assert e <= 1e-4
+
+
 def test_rays_in_sector_edge_planes_sums(torch_cuda):
     """Rays lying exactly in a sector-edge plane (and through the axis): the
     side they are given is a rounding tie, so compare what is unique: the FP
