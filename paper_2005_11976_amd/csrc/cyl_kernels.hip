@@ -794,21 +794,6 @@ struct Block {
     int hA, hB, tA, tB, rA, rB;
 };
 
-__device__ __forceinline__ Block block_of(const GeomDev &g, int b) {
-    Block B;
-    const int ir = b % g.nbr;
-    const int rest = b / g.nbr;
-    const int itb = rest % g.nbt;
-    const int ihb = rest / g.nbt;
-    B.hA = ihb * g.bh;
-    B.hB = min(B.hA + g.bh, g.n_h);
-    B.tA = itb * g.bt;
-    B.tB = min(B.tA + g.bt, g.n_theta);
-    B.rA = ir * g.br;
-    B.rB = min(B.rA + g.br, g.n_r);
-    return B;
-}
-
 // Projection of one bounding point of the block's convex hull
 // slab x wedge x disc(r_B) in view V, for point index `pt` (two z levels per
 // polygon corner; the polygon circumscribes the outer arc).  Points with
@@ -968,9 +953,6 @@ __device__ __forceinline__ bool clip_block(const GeomDev &g, const Tabs &T, cons
     return s1 > s0;
 }
 
-// Trace ray (u, v) of view V through block B and add t_jm * yj (and t_jm if
-// COLSUM) into the block accumulators; cells outside the block (rounding at
-// its faces) go to the spare slot acc[ncell].
 // Accumulator slot of block-local cell (h, t, q): rows of br + 1 and planes of
 // bt (br + 1) + 1 words, odd strides so neighbouring cells in theta and h fall
 // in different LDS banks.
@@ -982,15 +964,15 @@ __device__ __forceinline__ int slot(const Block &B, int h, int t, int q) {
 
 __device__ __forceinline__ int block_slots(const Block &B) { return slot(B, B.hB - B.hA, 0, 0) + 1; }
 
-// COLSUM = false: c_m += t_jm y_j into FP32 accumulators acc_c (LDS float atomics).
-// COLSUM = true (SART): c_m and n_m in one 64-bit fixed-point accumulator per
-// cell, acc64 = c 2^32 + n with c = sum rint(t_jm y_j cscale) and
+// Trace ray (u, v) of view V through block B (a block or a super-block) and
+// add its lengths into one 64-bit fixed-point accumulator per cell,
+// acc64 = c 2^32 + n with c = sum rint(t_jm y_j cscale) and
 // n = sum rint(t_jm nscale): one integer LDS atomic per step, and integer sums
 // do not depend on their order.  The scales keep |c| and n below 2^31 (see
-// sart_scales), so the low word never carries into the high word; ycs = y_j cscale.
-template <bool COLSUM>
+// sart_scales), so the low word never carries into the high word; yj is
+// y_j cscale, and nscale = 0 accumulates c alone.
 __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const ViewDev &V, const Block &B, int u,
-                                       int v, float yj, float *acc_c, unsigned long long *acc64, float nscale) {
+                                       int v, float yj, unsigned long long *acc64, float nscale) {
     RayF r;
     double dx, dy, dz, tc;
     ray_geom<false>(g, T, V, u, v, r, dx, dy, dz, tc);  // the block clip bounds the walk
@@ -1029,22 +1011,17 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Vi
     const int ps = (B.tB - B.tA) * rs + 1;
     const int off = B.hA * ps + B.tA * rs + B.rA;
     struct Scatter {
-        float *cb;
         unsigned long long *b64;
         int ps, rs;
         float yj, nscale;
         __device__ __forceinline__ void operator()(int h, int t, int q, float len) {
             const int loc = (int)(__umul24(h, ps) + __umul24(t, rs)) + q;
-            if (COLSUM) {
-                const unsigned int c = (unsigned int)round_half_up(len * yj);
-                const unsigned int n = (unsigned int)round_half_up(len * nscale);
-                atomicAdd(&b64[loc], ((unsigned long long)c << 32) | n);
-            } else {
-                atomicAdd(&cb[loc], len * yj);
-            }
+            const unsigned int c = (unsigned int)round_half_up(len * yj);
+            const unsigned int n = (unsigned int)round_half_up(len * nscale);
+            atomicAdd(&b64[loc], ((unsigned long long)c << 32) | n);
         }
         __device__ __forceinline__ void late() {}
-    } visit{COLSUM ? nullptr : acc_c - off, COLSUM ? acc64 - off : nullptr, ps, rs, yj, nscale};
+    } visit{acc64 - off, ps, rs, yj, nscale};
     const Box bx{B.hA, B.hB - B.hA, B.tA, B.tB - B.tA, B.rA, B.rB - B.rA};
     for (int piece = 0; piece < 2; ++piece) {
         const float a0 = piece ? pb0 : pa0, a1 = piece ? pb1 : pa1;
@@ -1065,85 +1042,6 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Vi
     }
 }
 
-// Plain transpose A^T y.  Workgroup of 4 waves; each wave owns one block of
-// cells and loops over the views, over the detector pixels of the block
-// footprint, traces each ray through the block hull and accumulates
-// c_m = sum t_jm y_j in wave-private LDS (float atomics; deterministic, as no
-// two waves share a slot).  vol = (accumulate ? vol : 0) + c.
-template <int VT, int PT>
-__global__ __launch_bounds__(256) void bp_kernel(const BpLaunch L) {
-    const BpItem &item = L.item[blockIdx.y];
-    if ((int)blockIdx.x >= item.nwg) return;
-    const GeomDev &g = item.g;
-    const void *__restrict__ y = item.y;
-    void *__restrict__ vol = item.vol;
-    const int view_begin = item.view_begin, view_end = item.view_end;
-    const int accumulate = item.flags & 1;
-    extern __shared__ float2 smem[];
-    const Tabs T = stage_tables(g, smem, false);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int slots = g.bh * (g.bt * (g.br + 1) + 1) + 1;
-    float *acc_c = (float *)(smem + table_floats2(g, false)) + wave * slots;
-    // dispatch order: outer rings first (their blocks carry the most work), and
-    // the 4 waves of a workgroup take 4 blocks stacked in h (similar work, so
-    // the workgroup's LDS is not held by one slow wave)
-    const int nhg = (g.nbh + 3) / 4;
-    const int per_ring = g.nbt * nhg;
-    const int ibr = g.nbr - 1 - (int)blockIdx.x / per_ring;
-    const int rem = (int)blockIdx.x % per_ring;
-    const int ibh = (rem % nhg) * 4 + wave;
-    const bool live = ibh < g.nbh;
-    const int b = ((live ? ibh : 0) * g.nbt + rem / nhg) * g.nbr + ibr;
-    const Block B = block_of(g, b);
-    const int wt = B.tB - B.tA, wr = B.rB - B.rA;
-    const int ncell = (B.hB - B.hA) * wt * wr;
-    const int nslot = block_slots(B);
-    for (int i = lane; i < nslot; i += 64) acc_c[i] = 0.0f;
-    __syncthreads();
-    if (live) {
-        for (int k = view_begin; k < view_end; ++k) {
-            const ViewDev &V = g.views[k];
-            int u0, u1, v0, v1;
-            if (!footprint(g, T, V, B, u0, u1, v0, v1)) continue;
-            u0 = __builtin_amdgcn_readfirstlane(u0);
-            u1 = __builtin_amdgcn_readfirstlane(u1);
-            v0 = __builtin_amdgcn_readfirstlane(v0);
-            v1 = __builtin_amdgcn_readfirstlane(v1);
-            const int nu = u1 - u0 + 1;
-            const int npix = nu * (v1 - v0 + 1);
-            for (int base = 0; base < npix; base += 64) {
-                const int p = base + lane;
-                if (p >= npix) continue;
-                const int v = v0 + p / nu;
-                const int u = u0 + p % nu;
-                const float yj = Store<PT>::ld(y, ((size_t)k * g.rows + v) * g.cols + u);
-                if (yj == 0.0f) continue;
-                bp_ray<false>(g, T, V, B, u, v, yj, acc_c, nullptr, 1.0f);
-            }
-        }
-    }
-    __syncthreads();
-    if (!live) return;
-    // cell i = (h wt + t) wr + q; a lane steps 64 cells, 64 = dh (wt wr) + dt wr
-    // + dq, added digit by digit with carries (one division per block, not
-    // three per cell)
-    const int dq = 64 % wr, dt = (64 / wr) % wt, dh = 64 / (wr * wt);
-    int q = lane % wr, t = (lane / wr) % wt, h = lane / (wr * wt);
-    for (int i = lane; i < ncell; i += 64) {
-        if (i != lane) {
-            q += dq;
-            const int c1 = q >= wr ? 1 : 0;
-            q -= c1 ? wr : 0;
-            t += dt + c1;
-            const int c2 = t >= wt ? 1 : 0;
-            t -= c2 ? wt : 0;
-            h += dh + c2;
-        }
-        const size_t gi = ((size_t)(B.hA + h) * g.n_theta + (B.tA + t)) * g.n_r + (B.rA + q);
-        const float base = accumulate ? Store<VT>::ld(vol, gi) : 0.0f;
-        Store<VT>::st(vol, gi, base + acc_c[slot(B, h, t, q)]);
-    }
-}
 
 // Super-block of the SART update: 4 blocks of the back-projection
 // decomposition merged by factors ft (theta) x fr (r) x fh (h) = 4.  Merging
@@ -1168,6 +1066,16 @@ __host__ __device__ __forceinline__ SbShape sb_shape(const GeomDev &g) {
     return s;
 }
 
+// Bound on the length of a ray inside one cell of block B (the cell's
+// diameter, with the outer radius of the block for the arc), inflated by 1e-3.
+__device__ __forceinline__ float cell_diameter(const GeomDev &g, const Tabs &T, const Block &B) {
+    const float rB = T.r[B.rB].x;
+    const float dxy = g.dtheta >= 3.14159265f
+                          ? 2.0f * rB
+                          : sqrtf(g.dr * g.dr + 4.0f * rB * rB * sinf(0.5f * g.dtheta) * sinf(0.5f * g.dtheta));
+    return sqrtf(g.dh * g.dh + dxy * dxy) * 1.001f;
+}
+
 // Fixed-point scales of a super-block's SART update, {nscale, 1/nscale,
 // cscale, 1/cscale}, computed by one wave.  With D the cell diameter (a bound
 // on any chord through one cell), R_k the bound on the rays of view k that
@@ -1182,11 +1090,7 @@ __host__ __device__ __forceinline__ SbShape sb_shape(const GeomDev &g) {
 __device__ float4 sart_scales(const GeomDev &g, const Tabs &T, const Block &B, const float *__restrict__ rho,
                               const int32_t *__restrict__ vlist, int view_begin, int view_end) {
     const int lane = threadIdx.x & 63;
-    const float rB = T.r[B.rB].x;
-    const float dxy = g.dtheta >= 3.14159265f
-                          ? 2.0f * rB
-                          : sqrtf(g.dr * g.dr + 4.0f * rB * rB * sinf(0.5f * g.dtheta) * sinf(0.5f * g.dtheta));
-    const float dcell = sqrtf(g.dh * g.dh + dxy * dxy) * 1.001f;
+    const float dcell = cell_diameter(g, T, B);
     const size_t npv = (size_t)g.rows * g.cols;
     float nb = 0.0f, cb = 0.0f;
     for (int k = view_begin; k < view_end; ++k) {
@@ -1223,17 +1127,56 @@ __device__ float4 sart_scales(const GeomDev &g, const Tabs &T, const Block &B, c
     return sc;
 }
 
-// SART update on super-blocks.  With integer (c, n) sums the order of the
+// Fixed-point scale of a super-block's plain transpose, {cscale, 1/cscale},
+// computed by one wave: |c_m| <= D sum_k R_k m_k as for sart_scales, with
+// m_k the largest |y| over view k's footprint box (read pixel by pixel: the
+// caller's projections carry no tile maxima).
+template <int PT>
+__device__ float2 plain_scales(const GeomDev &g, const Tabs &T, const Block &B, const void *__restrict__ y,
+                               int view_begin, int view_end) {
+    const int lane = threadIdx.x & 63;
+    const float dcell = cell_diameter(g, T, B);
+    float cb = 0.0f;
+    for (int k = view_begin; k < view_end; ++k) {
+        float rays;
+        int u0, u1, v0, v1;
+        if (!footprint(g, T, g.views[k], B, u0, u1, v0, v1, dcell, &rays)) continue;
+        u0 = __builtin_amdgcn_readfirstlane(u0);
+        u1 = __builtin_amdgcn_readfirstlane(u1);
+        v0 = __builtin_amdgcn_readfirstlane(v0);
+        v1 = __builtin_amdgcn_readfirstlane(v1);
+        const int nu = u1 - u0 + 1, npix = nu * (v1 - v0 + 1);
+        const size_t vb = (size_t)k * g.rows;
+        float ymax = 0.0f;
+        for (int p = lane; p < npix; p += 64)
+            ymax = fmaxf(ymax, fabsf(Store<PT>::ld(y, (vb + v0 + p / nu) * g.cols + u0 + p % nu)));
+        cb = fmaf(rays, wave_max(ymax), cb);
+    }
+    float2 sc = make_float2(1.0f, 1.0f);
+    if (cb > 0.0f) {
+        int e;
+        frexpf(1073741824.0f / (dcell * cb), &e);
+        sc.x = ldexpf(1.0f, e - 1);
+        sc.y = ldexpf(1.0f, 1 - e);
+    }
+    return sc;
+}
+
+// Back-projection on super-blocks.  With integer sums the order of the
 // additions does not matter, so the 4 waves of a workgroup share one
 // accumulator for a super-block, and a ray that crosses several of its
 // blocks is set up once.  The waves take batches of 64
 // footprint pixels from an LDS counter that runs across the views of the
-// update: each wave walks the views in the same order and computes the same
+// call: each wave walks the views in the same order and computes the same
 // footprints (same code, same inputs), and so finds the same batch boundaries
 // without synchronising.  Wave 0 alone finds the fixed-point scales.
-// vol += lam * wv * c / n where n > 0.
-template <int VT>
-__global__ __launch_bounds__(256) void sart_bp_kernel(const BpLaunch L) {
+// SART: y holds the FP32 residual images of the update's positions (then
+// their tile maxima), each cell accumulates (c, n) and
+// vol += lam * wv * c / n where n > 0.  Plain transpose: y holds the caller's
+// projections (type PT, [n_views][rows][cols]), each cell accumulates c alone
+// (n scale 0) and vol = (accumulate ? vol : 0) + c for every cell.
+template <int VT, int PT, bool SART>
+__device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
     const BpItem &item = L.item[blockIdx.y];
     if ((int)blockIdx.x >= item.nwg) return;
     const GeomDev &g = item.g;
@@ -1241,7 +1184,7 @@ __global__ __launch_bounds__(256) void sart_bp_kernel(const BpLaunch L) {
     void *__restrict__ vol = item.vol;
     const void *__restrict__ vw = item.vw;
     const int view_begin = item.view_begin, view_end = item.view_end;
-    const int nonneg = (item.flags >> 1) & 1, vwt = item.flags >> 8;
+    const int accumulate = item.flags & 1, nonneg = (item.flags >> 1) & 1, vwt = item.flags >> 8;
     const float lam = item.lam;
     const int32_t *__restrict__ vlist = item.views;
     extern __shared__ float2 smem[];
@@ -1276,7 +1219,13 @@ __global__ __launch_bounds__(256) void sart_bp_kernel(const BpLaunch L) {
     const size_t npv = (size_t)g.rows * g.cols;
     // wave 0 finds the fixed-point scales and shares them through LDS
     if (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6) == 0) {
-        const float4 sc = sart_scales(g, T, B, rho, vlist, view_begin, view_end);
+        float4 sc;
+        if (SART) {
+            sc = sart_scales(g, T, B, rho, vlist, view_begin, view_end);
+        } else {
+            const float2 c = plain_scales<PT>(g, T, B, item.y, view_begin, view_end);
+            sc = make_float4(0.0f, 0.0f, c.x, c.y);
+        }
         if (lane == 0) {
             scales[0] = sc.x;
             scales[1] = sc.y;
@@ -1319,8 +1268,10 @@ __global__ __launch_bounds__(256) void sart_bp_kernel(const BpLaunch L) {
             const int view = vlist ? vlist[k] : k;
             const int v = v0 + p / nu;
             const int u = u0 + p % nu;
-            const float yj = rho[(size_t)(k - view_begin) * npv + (size_t)v * g.cols + u];
-            bp_ray<true>(g, T, g.views[view], B, u, v, yj * cscale, nullptr, acc64, nscale);
+            const float yj = SART ? rho[(size_t)(k - view_begin) * npv + (size_t)v * g.cols + u]
+                                  : Store<PT>::ld(item.y, (size_t)k * npv + (size_t)v * g.cols + u);
+            if (SART || yj != 0.0f)
+                bp_ray(g, T, g.views[view], B, u, v, yj * cscale, acc64, nscale);
         }
     }
     __syncthreads();
@@ -1339,6 +1290,12 @@ __global__ __launch_bounds__(256) void sart_bp_kernel(const BpLaunch L) {
             h += dh + c2;
         }
         const unsigned long long a = acc64[slot(B, h, t, q)];
+        if (!SART) {
+            const size_t gi = ((size_t)(B.hA + h) * g.n_theta + (B.tA + t)) * g.n_r + (B.rA + q);
+            const float c = (float)(int)(unsigned int)(a >> 32) * inv_cscale;
+            Store<VT>::st(vol, gi, (accumulate ? Store<VT>::ld(vol, gi) : 0.0f) + c);
+            continue;
+        }
         const float n = (float)(unsigned int)a * inv_nscale;
         if (n > 0.0f) {
             const size_t gi = ((size_t)(B.hA + h) * g.n_theta + (B.tA + t)) * g.n_r + (B.rA + q);
@@ -1349,6 +1306,18 @@ __global__ __launch_bounds__(256) void sart_bp_kernel(const BpLaunch L) {
             Store<VT>::st(vol, gi, m);
         }
     }
+}
+
+// SART update (Eq. 7 over the update's views) on super-blocks.
+template <int VT>
+__global__ __launch_bounds__(256) void sart_bp_kernel(const BpLaunch L) {
+    superblock_bp<VT, CYL_F32, true>(L);
+}
+
+// Plain transpose A^T y over views [view_begin, view_end) on super-blocks.
+template <int VT, int PT>
+__global__ __launch_bounds__(256) void bp_kernel(const BpLaunch L) {
+    superblock_bp<VT, PT, false>(L);
 }
 
 // ------------------------------------------------------------ elementwise
@@ -1386,9 +1355,12 @@ int launch_record(const cyl_geom *G, int view, const int32_t *rowptr, int32_t *c
     return launch_check("record");
 }
 
-static size_t bp_lds_bytes(const GeomDev &g, bool sart) {
+// LDS of a super-block launch: the sector-edge table and 64-bit accumulator
+// words for 4 blocks of bh slabs plus one spare word each (the super-block's
+// slots, its batch counter and its two scale words fit in these).
+static size_t bp_lds_bytes(const GeomDev &g) {
     return sizeof(float2) * (size_t)(g.n_theta + 1) +
-           4 * sizeof(float) * (size_t)(g.bh * (g.bt * (g.br + 1) + 1) + 1) * (sart ? 2 : 1);
+           sizeof(unsigned long long) * 4 * (size_t)(g.bh * (g.bt * (g.br + 1) + 1) + 1);
 }
 
 // Rays per item below which each ray is split over neighbouring lanes so one
@@ -1430,12 +1402,9 @@ static BpItem bp_item(const cyl_geom *G, const void *y, int vb, int ve, void *vo
     it.views = views;
     it.view_begin = vb;
     it.view_end = ve;
-    if (sart) {
-        const SbShape sb = sb_shape(g);
-        it.nwg = sb.nsr * sb.nst * sb.nsh;
-    } else {
-        it.nwg = g.nbr * g.nbt * ((g.nbh + 3) / 4);
-    }
+    const SbShape sb = sb_shape(g);
+    it.nwg = sb.nsr * sb.nst * sb.nsh;
+    (void)sart;
     it.flags = (accumulate ? 1 : 0) | (nonneg ? 2 : 0) | (vwt << 8);
     it.lam = lam;
     return it;
@@ -1564,7 +1533,7 @@ static void launch_bp_batch(const BpLaunch &L, const cyl_geom *const *geoms, int
     LaunchShape sh;
     for (int i = 0; i < L.n; ++i) {
         sh.maxwg = std::max(sh.maxwg, L.item[i].nwg);
-        sh.lds = std::max(sh.lds, bp_lds_bytes(geoms[i]->dev, sart));
+        sh.lds = std::max(sh.lds, bp_lds_bytes(geoms[i]->dev));
     }
     switch (vt) {
         case CYL_F32: launch_bp_v<CYL_F32>(L, sh, pt, sart, st); break;
