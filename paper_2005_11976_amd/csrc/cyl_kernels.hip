@@ -1,7 +1,7 @@
 // HIP kernels of libcyl (gfx950): cylindrical Siddon traversal, forward
-// projection with the SART residual epilogue, block-owned back-projection
-// with the SART update epilogue, closed-form row sums, and the C entry points
-// that launch them.
+// projection with the SART residual epilogue, back-projection on shared
+// super-blocks of cells (the plain transpose, or the SART update epilogue),
+// closed-form row sums, and the C entry points that launch them.
 //
 // Ray model (Sec. 2.2, Eq. 6): one ray per pixel from the source to the pixel
 // centre; t_jl is the exact length of that segment inside ring-sector cell l
@@ -1191,7 +1191,7 @@ __device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
     const Tabs T = stage_tables(g, smem, false);
     const int lane = threadIdx.x & 63;
     unsigned long long *acc64 = (unsigned long long *)(smem + table_floats2(g, false));
-    // super-block: outer rings first, as for bp_kernel
+    // super-blocks: outer rings first (their blocks carry the most work)
     const SbShape sb = sb_shape(g);
     const int per_ring = sb.nst * sb.nsh;
     const int isr = sb.nsr - 1 - (int)blockIdx.x / per_ring;
