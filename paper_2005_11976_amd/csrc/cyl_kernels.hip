@@ -128,8 +128,17 @@ __device__ __forceinline__ int round_half_up(float x) {
 struct Tabs {
     const float2 *r;   // n_r + 1 shell radii (hi, lo)
     const float2 *h;   // n_h + 1 axial planes (hi, lo)
-    const float2 *cs;  // n_theta + 1 sector edges (cos, sin)
+    const float2 *cs;  // sector edges cs_lo .. cs_lo + cs_n (cos, sin)
+    int cs_lo, cs_n;
 };
+
+// Sector edge b of a table that may hold only part of the edges (a
+// super-block's wedge).  A walk reads the edge ahead before it checks its
+// box, so on the step that leaves the box b may lie outside the table; that
+// read is clamped to the last entry and its value is never used.
+__device__ __forceinline__ float2 edge_at(const Tabs &T, int b) {
+    return T.cs[min((unsigned)(b - T.cs_lo), (unsigned)T.cs_n)];
+}
 
 __device__ __forceinline__ size_t table_floats2(const GeomDev &g, bool all = true) {
     return (all ? (size_t)(g.n_r + 1) + (g.n_h + 1) : 0) + (g.n_theta + 1);
@@ -147,6 +156,21 @@ __device__ __forceinline__ Tabs stage_tables(const GeomDev &g, float2 *smem, boo
     T.r = all ? smem : g.r_tab;
     T.h = all ? smem + nr : g.h_tab;
     T.cs = smem + nr + nh;
+    T.cs_lo = 0;
+    T.cs_n = g.n_theta;
+    return T;
+}
+
+// Sector edges lo .. hi only (a super-block's wedge), staged in LDS, with the
+// radii and planes left in global memory; the caller synchronises.
+__device__ __forceinline__ Tabs stage_edges(const GeomDev &g, float2 *smem, int lo, int hi) {
+    for (int i = threadIdx.x; i <= hi - lo; i += blockDim.x) smem[i] = g.cs_tab[lo + i];
+    Tabs T;
+    T.r = g.r_tab;
+    T.h = g.h_tab;
+    T.cs = smem;
+    T.cs_lo = lo;
+    T.cs_n = hi - lo;
     return T;
 }
 
@@ -515,7 +539,7 @@ __device__ __forceinline__ float edge_next(const ViewDev &V, const GeomDev &g, c
 // before the visitor so that its latency overlaps the visitor's work.  Plane
 // and shell candidates after their own event are monotone in the index, so
 // only the first ones and the edge candidates are clamped to s.
-template <bool CHECK_T, class Visit>
+template <bool CHECK_T, bool PART, class Visit>
 __device__ __forceinline__ void traverse(const GeomDev &g, const Tabs &T, const ViewDev &V, const RayF &r, float s,
                                          const float s_end, int ih, int it, int ir, const Box &bx, Visit &visit) {
     const int nt = g.n_theta;
@@ -527,7 +551,7 @@ __device__ __forceinline__ void traverse(const GeomDev &g, const Tabs &T, const 
     if (r.flags & RAY_THRU)
         s_t = s < 0.0f ? 0.0f : CYL_INF;
     else
-        s_t = edge_next(V, g, w, r, T.cs[it + w.up_t], it + w.up_t, s, true);
+        s_t = edge_next(V, g, w, r, PART ? edge_at(T, it + w.up_t) : T.cs[it + w.up_t], it + w.up_t, s, true);
     const int max_steps = 2 * g.n_r + nt + g.n_h + 8;
     for (int n = 0; n < max_steps; ++n) {
         const float sn = vmin(vmin3(s_z, s_r, s_t), s_end);
@@ -537,7 +561,7 @@ __device__ __forceinline__ void traverse(const GeomDev &g, const Tabs &T, const 
         int itn = it + (ev_t ? w.tstep : 0);
         itn -= ((unsigned)itn >= (unsigned)nt) ? w.twrap : 0;
         const int be = itn + w.up_t;
-        const float2 cse = T.cs[be];
+        const float2 cse = PART ? edge_at(T, be) : T.cs[be];
         visit(ih, it, ir, sn - s);
         s = sn;
         ih += ev_z ? w.dir_h : 0;
@@ -650,7 +674,7 @@ __device__ __forceinline__ float fp_piece(const GeomDev &g, const Tabs &T, const
         __device__ __forceinline__ void late() {}
     } visit{vol, g.n_theta, g.n_r, g.n_theta * g.n_r, 0.0f, 0.0f, 0.0f};
     const Box bx{0, g.n_h, 0, g.n_theta, -1, g.n_r + 1};
-    traverse<false>(g, T, V, r, a0, a1, ih, it, ir, bx, visit);
+    traverse<false, false>(g, T, V, r, a0, a1, ih, it, ir, bx, visit);
     return fmaf(visit.plen, visit.pval, visit.acc);
 }
 
@@ -758,7 +782,7 @@ __global__ __launch_bounds__(256) void record_kernel(GeomDev g, int view, int fi
         int ih, it, ir;
         cell_at(g, r, r.s_in, ih, it, ir);
         const Box bx{0, g.n_h, 0, g.n_theta, -1, g.n_r + 1};
-        traverse<false>(g, T, V, r, r.s_in, r.s_out, ih, it, ir, bx, rec);
+        traverse<false, false>(g, T, V, r, r.s_in, r.s_out, ih, it, ir, bx, rec);
     }
     if (!fill) {
         counts[pix] = rec.n;
@@ -912,6 +936,7 @@ __device__ bool footprint(const GeomDev &g, const Tabs &T, const ViewDev &V, con
 
 // Parameter interval of the ray inside the block hull (slab x wedge x disc),
 // from the same crossing formulas as the traversal.
+template <bool PART>
 __device__ __forceinline__ bool clip_block(const GeomDev &g, const Tabs &T, const ViewDev &V, const RayF &r,
                                            const Block &B, float &s0, float &s1) {
     s0 = r.s_in;
@@ -936,7 +961,7 @@ __device__ __forceinline__ bool clip_block(const GeomDev &g, const Tabs &T, cons
         // lower edge: n_A . p >= 0 ; upper edge: n_B . p <= 0
         for (int e = 0; e < 2; ++e) {
             const int eb = e == 0 ? B.tA : B.tB;
-            const EdgeX x = edge_cross(g, V, r, T.cs[eb], eb);
+            const EdgeX x = edge_cross(g, V, r, PART ? edge_at(T, eb) : T.cs[eb], eb);
             const float sg = e == 0 ? 1.0f : -1.0f;
             if (x.ne == 0.0f) {
                 // parallel to the edge line: a ray on the line belongs to the
@@ -971,6 +996,7 @@ __device__ __forceinline__ int block_slots(const Block &B) { return slot(B, B.hB
 // do not depend on their order.  The scales keep |c| and n below 2^31 (see
 // sart_scales), so the low word never carries into the high word; yj is
 // y_j cscale, and nscale = 0 accumulates c alone.
+template <bool PART>
 __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const ViewDev &V, const Block &B, int u,
                                        int v, float yj, unsigned long long *acc64, float nscale) {
     RayF r;
@@ -978,7 +1004,7 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Vi
     ray_geom<false>(g, T, V, u, v, r, dx, dy, dz, tc);  // the block clip bounds the walk
     if (!(r.flags & RAY_HIT)) return;
     float s0, s1;
-    if (!clip_block(g, T, V, r, B, s0, s1)) return;
+    if (!clip_block<PART>(g, T, V, r, B, s0, s1)) return;
     // the hull includes the block's inner hole r < r_A: split the interval
     // there so the walk covers the block cells only
     float pa0 = s0, pa1 = s1, pb0 = 1.0f, pb1 = 0.0f;
@@ -1038,7 +1064,7 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Vi
             if (dhi < 0) dhi += g.n_theta;
             it = dlo <= dhi ? B.tA : B.tB - 1;
         }
-        traverse<true>(g, T, V, r, a0, a1, ih, it, ir, bx, visit);
+        traverse<true, PART>(g, T, V, r, a0, a1, ih, it, ir, bx, visit);
     }
 }
 
@@ -1064,6 +1090,12 @@ __host__ __device__ __forceinline__ SbShape sb_shape(const GeomDev &g) {
     s.nst = (g.nbt + s.ft - 1) / s.ft;
     s.nsr = (g.nbr + s.fr - 1) / s.fr;
     return s;
+}
+
+// Sector-edge entries a super-block stages in LDS: its wedge's edges, at most
+// ft bt + 1.
+__host__ __device__ __forceinline__ int sb_edge_words(const GeomDev &g, const SbShape &sb) {
+    return sb.ft * g.bt + 1;
 }
 
 // Bound on the length of a ray inside one cell of block B (the cell's
@@ -1175,7 +1207,10 @@ __device__ float2 plain_scales(const GeomDev &g, const Tabs &T, const Block &B, 
 // vol += lam * wv * c / n where n > 0.  Plain transpose: y holds the caller's
 // projections (type PT, [n_views][rows][cols]), each cell accumulates c alone
 // (n scale 0) and vol = (accumulate ? vol : 0) + c for every cell.
-template <int VT, int PT, bool SART>
+// PART: stage only the super-block's sector edges (a grid whose full edge
+// table would leave room for fewer than 4 workgroups per CU); otherwise the
+// whole table, read without the clamp.
+template <int VT, int PT, bool SART, bool PART>
 __device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
     const BpItem &item = L.item[blockIdx.y];
     if ((int)blockIdx.x >= item.nwg) return;
@@ -1188,9 +1223,9 @@ __device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
     const float lam = item.lam;
     const int32_t *__restrict__ vlist = item.views;
     extern __shared__ float2 smem[];
-    const Tabs T = stage_tables(g, smem, false);
+    Tabs T;
+    if (!PART) T = stage_tables(g, smem, false);
     const int lane = threadIdx.x & 63;
-    unsigned long long *acc64 = (unsigned long long *)(smem + table_floats2(g, false));
     // super-blocks: outer rings first (their blocks carry the most work)
     const SbShape sb = sb_shape(g);
     const int per_ring = sb.nst * sb.nsh;
@@ -1206,6 +1241,12 @@ __device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
     B.rB = min(B.rA + sb.fr * g.br, g.n_r);
     const int wt = B.tB - B.tA, wr = B.rB - B.rA;
     const int ncell = (B.hB - B.hA) * wt * wr;
+    // the walks are boxed to the super-block, so they read the sector edges
+    // tA .. tB only: PART stages just those (sb_edge_words entries at most),
+    // else the whole table (staged above); then the accumulator words
+    if (PART) T = stage_edges(g, smem, B.tA, B.tB);
+    unsigned long long *acc64 =
+        (unsigned long long *)(smem + (PART ? sb_edge_words(g, sb) : table_floats2(g, false)));
     // The allocation holds 4 blocks of bh slabs plus one spare word each:
     // 4 bh bt br + 4 bh bt + 4 bh + 4 words, at least 3 more than the
     // super-block's (fh bh)((ft bt)(fr br + 1) + 1) + 1 slots (fh ft fr = 4,
@@ -1271,7 +1312,7 @@ __device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
             const float yj = SART ? rho[(size_t)(k - view_begin) * npv + (size_t)v * g.cols + u]
                                   : Store<PT>::ld(item.y, (size_t)k * npv + (size_t)v * g.cols + u);
             if (SART || yj != 0.0f)
-                bp_ray(g, T, g.views[view], B, u, v, yj * cscale, acc64, nscale);
+                bp_ray<PART>(g, T, g.views[view], B, u, v, yj * cscale, acc64, nscale);
         }
     }
     __syncthreads();
@@ -1309,15 +1350,15 @@ __device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
 }
 
 // SART update (Eq. 7 over the update's views) on super-blocks.
-template <int VT>
-__global__ __launch_bounds__(256) void sart_bp_kernel(const BpLaunch L) {
-    superblock_bp<VT, CYL_F32, true>(L);
+template <int VT, bool PART>
+__global__ __launch_bounds__(256, PART ? 4 : 1) void sart_bp_kernel(const BpLaunch L) {
+    superblock_bp<VT, CYL_F32, true, PART>(L);
 }
 
 // Plain transpose A^T y over views [view_begin, view_end) on super-blocks.
-template <int VT, int PT>
-__global__ __launch_bounds__(256) void bp_kernel(const BpLaunch L) {
-    superblock_bp<VT, PT, false>(L);
+template <int VT, int PT, bool PART>
+__global__ __launch_bounds__(256, PART ? 4 : 1) void bp_kernel(const BpLaunch L) {
+    superblock_bp<VT, PT, false, PART>(L);
 }
 
 // ------------------------------------------------------------ elementwise
@@ -1355,13 +1396,18 @@ int launch_record(const cyl_geom *G, int view, const int32_t *rowptr, int32_t *c
     return launch_check("record");
 }
 
-// LDS of a super-block launch: the sector-edge table and 64-bit accumulator
-// words for 4 blocks of bh slabs plus one spare word each (the super-block's
-// slots, its batch counter and its two scale words fit in these).
-static size_t bp_lds_bytes(const GeomDev &g) {
-    return sizeof(float2) * (size_t)(g.n_theta + 1) +
+// LDS of a super-block launch: the sector edges (the whole table, or the
+// super-block's part) and 64-bit accumulator words for 4 blocks of bh slabs
+// plus one spare word each (the super-block's slots, its batch counter and its
+// two scale words fit in these).
+static size_t bp_lds_bytes(const GeomDev &g, bool part) {
+    const size_t edges = part ? (size_t)sb_edge_words(g, sb_shape(g)) : (size_t)g.n_theta + 1;
+    return sizeof(float2) * edges +
            sizeof(unsigned long long) * 4 * (size_t)(g.bh * (g.bt * (g.br + 1) + 1) + 1);
 }
+
+// LDS per workgroup that lets 4 workgroups of 4 waves share a CU's 160 KiB.
+constexpr size_t kLdsFor4 = 160 * 1024 / 4;
 
 // Rays per item below which each ray is split over neighbouring lanes so one
 // view still fills the GPU.  Chosen per item, so an item's result does not
@@ -1415,6 +1461,7 @@ static BpItem bp_item(const cyl_geom *G, const void *y, int vb, int ve, void *vo
 struct LaunchShape {
     int maxwg = 0;
     size_t lds = 0;
+    bool part = false;  // BP: super-blocks stage only their own sector edges
 };
 
 template <int VT, int PT>
@@ -1509,10 +1556,14 @@ static void store_i32(int32_t *dst, const int32_t *src, int n, hipStream_t st) {
 template <int VT, int PT>
 static void launch_bp_t(const BpLaunch &L, const LaunchShape &sh, bool sart, hipStream_t st) {
     dim3 grid(sh.maxwg, L.n);
-    if (sart)
-        hipLaunchKernelGGL((sart_bp_kernel<VT>), grid, dim3(256), sh.lds, st, L);
+    if (sart && sh.part)
+        hipLaunchKernelGGL((sart_bp_kernel<VT, true>), grid, dim3(256), sh.lds, st, L);
+    else if (sart)
+        hipLaunchKernelGGL((sart_bp_kernel<VT, false>), grid, dim3(256), sh.lds, st, L);
+    else if (sh.part)
+        hipLaunchKernelGGL((bp_kernel<VT, PT, true>), grid, dim3(256), sh.lds, st, L);
     else
-        hipLaunchKernelGGL((bp_kernel<VT, PT>), grid, dim3(256), sh.lds, st, L);
+        hipLaunchKernelGGL((bp_kernel<VT, PT, false>), grid, dim3(256), sh.lds, st, L);
 }
 
 template <int VT>
@@ -1533,8 +1584,9 @@ static void launch_bp_batch(const BpLaunch &L, const cyl_geom *const *geoms, int
     LaunchShape sh;
     for (int i = 0; i < L.n; ++i) {
         sh.maxwg = std::max(sh.maxwg, L.item[i].nwg);
-        sh.lds = std::max(sh.lds, bp_lds_bytes(geoms[i]->dev));
+        sh.part = sh.part || bp_lds_bytes(geoms[i]->dev, false) > kLdsFor4;
     }
+    for (int i = 0; i < L.n; ++i) sh.lds = std::max(sh.lds, bp_lds_bytes(geoms[i]->dev, sh.part));
     switch (vt) {
         case CYL_F32: launch_bp_v<CYL_F32>(L, sh, pt, sart, st); break;
         case CYL_F16: launch_bp_v<CYL_F16>(L, sh, pt, sart, st); break;
