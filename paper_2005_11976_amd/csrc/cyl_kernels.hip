@@ -1069,23 +1069,27 @@ __device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Vi
 }
 
 
-// Super-block of the SART update: 4 blocks of the back-projection
-// decomposition merged by factors ft (theta) x fr (r) x fh (h) = 4.  Merging
+// Super-block of the back-projection: sbb = 4 or 8 blocks of the
+// decomposition merged by factors ft (theta) x fr (r) x fh (h) = sbb.  Merging
 // in theta and r cuts the pixels that must be set up more than merging in h
 // (rays are nearly level): on 256x720x128, 4.3 M (ray, block) pairs per view
-// against 6.0 M for 4 blocks stacked in h and 7.1 M for single blocks.  The
-// merged wedge stays within pi (the hull clip takes it as the intersection of
-// two half-planes) or covers the whole circle.  Four blocks' slots always hold
-// the merged block's, with words to spare.
+// for 2 x 2 x 1 against 6.0 M for 4 blocks stacked in h and 7.1 M for single
+// blocks; h takes the rest of the factor.  The merged wedge stays within pi
+// (the hull clip takes it as the intersection of two half-planes) or covers
+// the whole circle.  sbb blocks' slots always hold the merged block's, with
+// words to spare.
+// A super-block merges sbb = 4 or 8 blocks; its workgroup has one wave per
+// block (64 sbb lanes).
+
 struct SbShape {
     int fh, ft, fr, nsh, nst, nsr;
 };
 
-__host__ __device__ __forceinline__ SbShape sb_shape(const GeomDev &g) {
+__host__ __device__ __forceinline__ SbShape sb_shape(const GeomDev &g, int sbb) {
     SbShape s;
     s.ft = (g.nbt >= 2 && 2 * g.bt <= g.n_theta / 2) ? 2 : 1;
     s.fr = g.nbr >= 2 ? 2 : 1;
-    s.fh = 4 / (s.ft * s.fr);
+    s.fh = sbb / (s.ft * s.fr);
     s.nsh = (g.nbh + s.fh - 1) / s.fh;
     s.nst = (g.nbt + s.ft - 1) / s.ft;
     s.nsr = (g.nbr + s.fr - 1) / s.fr;
@@ -1210,7 +1214,7 @@ __device__ float2 plain_scales(const GeomDev &g, const Tabs &T, const Block &B, 
 // PART: stage only the super-block's sector edges (a grid whose full edge
 // table would leave room for fewer than 4 workgroups per CU); otherwise the
 // whole table, read without the clamp.
-template <int VT, int PT, bool SART, bool PART>
+template <int VT, int PT, bool SART, bool PART, int SBB>
 __device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
     const BpItem &item = L.item[blockIdx.y];
     if ((int)blockIdx.x >= item.nwg) return;
@@ -1227,7 +1231,8 @@ __device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
     if (!PART) T = stage_tables(g, smem, false);
     const int lane = threadIdx.x & 63;
     // super-blocks: outer rings first (their blocks carry the most work)
-    const SbShape sb = sb_shape(g);
+    constexpr int nthr = 64 * SBB;
+    const SbShape sb = sb_shape(g, SBB);
     const int per_ring = sb.nst * sb.nsh;
     const int isr = sb.nsr - 1 - (int)blockIdx.x / per_ring;
     const int rem = (int)blockIdx.x % per_ring;
@@ -1247,15 +1252,15 @@ __device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
     if (PART) T = stage_edges(g, smem, B.tA, B.tB);
     unsigned long long *acc64 =
         (unsigned long long *)(smem + (PART ? sb_edge_words(g, sb) : table_floats2(g, false)));
-    // The allocation holds 4 blocks of bh slabs plus one spare word each:
-    // 4 bh bt br + 4 bh bt + 4 bh + 4 words, at least 3 more than the
-    // super-block's (fh bh)((ft bt)(fr br + 1) + 1) + 1 slots (fh ft fr = 4,
-    // fh ft <= 4, fh <= 4).  Word nslot holds the batch counter, the next two
+    // The allocation holds sbb blocks of bh slabs plus one spare word each:
+    // sbb (bh bt br + bh bt + bh + 1) words, at least 3 more than the
+    // super-block's (fh bh)((ft bt)(fr br + 1) + 1) + 1 slots (fh ft fr = sbb,
+    // fh ft <= sbb, fh <= sbb).  Word nslot holds the batch counter, the next two
     // the fixed-point scales.
     const int nslot = block_slots(B);
     unsigned int *counter = (unsigned int *)(acc64 + nslot);
     float *scales = (float *)(acc64 + nslot + 1);
-    for (int i = threadIdx.x; i < nslot; i += 256) acc64[i] = 0ull;
+    for (int i = threadIdx.x; i < nslot; i += nthr) acc64[i] = 0ull;
     if (threadIdx.x == 0) *counter = 0u;
     const size_t npv = (size_t)g.rows * g.cols;
     // wave 0 finds the fixed-point scales and shares them through LDS
@@ -1316,11 +1321,11 @@ __device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
         }
     }
     __syncthreads();
-    // update: 256 lanes over the cells, i = (h wt + t) wr + q stepped by 256
-    const int dq = 256 % wr, dt = (256 / wr) % wt, dh = 256 / (wr * wt);
+    // update: nthr lanes over the cells, i = (h wt + t) wr + q stepped by nthr
+    const int dq = nthr % wr, dt = (nthr / wr) % wt, dh = nthr / (wr * wt);
     const int i0 = (int)threadIdx.x;
     int q = i0 % wr, t = (i0 / wr) % wt, h = i0 / (wr * wt);
-    for (int i = i0; i < ncell; i += 256) {
+    for (int i = i0; i < ncell; i += nthr) {
         if (i != i0) {
             q += dq;
             const int c1 = q >= wr ? 1 : 0;
@@ -1350,15 +1355,15 @@ __device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
 }
 
 // SART update (Eq. 7 over the update's views) on super-blocks.
-template <int VT, bool PART>
-__global__ __launch_bounds__(256, PART ? 4 : 1) void sart_bp_kernel(const BpLaunch L) {
-    superblock_bp<VT, CYL_F32, true, PART>(L);
+template <int VT, bool PART, int SBB>
+__global__ __launch_bounds__(64 * SBB, PART ? 4 : 1) void sart_bp_kernel(const BpLaunch L) {
+    superblock_bp<VT, CYL_F32, true, PART, SBB>(L);
 }
 
 // Plain transpose A^T y over views [view_begin, view_end) on super-blocks.
-template <int VT, int PT, bool PART>
-__global__ __launch_bounds__(256, PART ? 4 : 1) void bp_kernel(const BpLaunch L) {
-    superblock_bp<VT, PT, false, PART>(L);
+template <int VT, int PT, bool PART, int SBB>
+__global__ __launch_bounds__(64 * SBB, PART ? 4 : 1) void bp_kernel(const BpLaunch L) {
+    superblock_bp<VT, PT, false, PART, SBB>(L);
 }
 
 // ------------------------------------------------------------ elementwise
@@ -1397,17 +1402,27 @@ int launch_record(const cyl_geom *G, int view, const int32_t *rowptr, int32_t *c
 }
 
 // LDS of a super-block launch: the sector edges (the whole table, or the
-// super-block's part) and 64-bit accumulator words for 4 blocks of bh slabs
+// super-block's part) and 64-bit accumulator words for sbb blocks of bh slabs
 // plus one spare word each (the super-block's slots, its batch counter and its
 // two scale words fit in these).
-static size_t bp_lds_bytes(const GeomDev &g, bool part) {
-    const size_t edges = part ? (size_t)sb_edge_words(g, sb_shape(g)) : (size_t)g.n_theta + 1;
+static size_t bp_lds_bytes(const GeomDev &g, bool part, int sbb) {
+    const size_t edges = part ? (size_t)sb_edge_words(g, sb_shape(g, sbb)) : (size_t)g.n_theta + 1;
     return sizeof(float2) * edges +
-           sizeof(unsigned long long) * 4 * (size_t)(g.bh * (g.bt * (g.br + 1) + 1) + 1);
+           sizeof(unsigned long long) * sbb * (size_t)(g.bh * (g.bt * (g.br + 1) + 1) + 1);
 }
 
-// LDS per workgroup that lets 4 workgroups of 4 waves share a CU's 160 KiB.
-constexpr size_t kLdsFor4 = 160 * 1024 / 4;
+// LDS per workgroup of sbb waves that lets 16 waves (4 per SIMD) share a CU's
+// 160 KiB.
+static size_t lds_for_4(int sbb) { return (size_t)160 * 1024 * sbb / 16; }
+
+// Blocks per super-block of a grid: 8 up to 2^25 cells, else 4 (measured: 8
+// took the 256x720x128 update from 0.403 to 0.388 ms per view, unposed and
+// posed alike, and 4 kept the 512x1440x256 posed one at 3.05 ms against 3.61).
+// A property of the grid alone, so a scan's result does not depend on the
+// batch it is launched with; a launch holds items of one size.
+static int grid_sbb(const GeomDev &g) {
+    return (int64_t)g.n_h * g.n_theta * g.n_r > ((int64_t)1 << 25) ? 4 : 8;
+}
 
 // Rays per item below which each ray is split over neighbouring lanes so one
 // view still fills the GPU.  Chosen per item, so an item's result does not
@@ -1448,9 +1463,9 @@ static BpItem bp_item(const cyl_geom *G, const void *y, int vb, int ve, void *vo
     it.views = views;
     it.view_begin = vb;
     it.view_end = ve;
-    const SbShape sb = sb_shape(g);
-    it.nwg = sb.nsr * sb.nst * sb.nsh;
+    it.nwg = 0;  // set with the launch's super-block size (launch_bp_batch)
     (void)sart;
+    (void)g;
     it.flags = (accumulate ? 1 : 0) | (nonneg ? 2 : 0) | (vwt << 8);
     it.lam = lam;
     return it;
@@ -1462,6 +1477,7 @@ struct LaunchShape {
     int maxwg = 0;
     size_t lds = 0;
     bool part = false;  // BP: super-blocks stage only their own sector edges
+    int sbb = 4;        // BP: blocks per super-block (and waves per workgroup)
 };
 
 template <int VT, int PT>
@@ -1556,14 +1572,25 @@ static void store_i32(int32_t *dst, const int32_t *src, int n, hipStream_t st) {
 template <int VT, int PT>
 static void launch_bp_t(const BpLaunch &L, const LaunchShape &sh, bool sart, hipStream_t st) {
     dim3 grid(sh.maxwg, L.n);
-    if (sart && sh.part)
-        hipLaunchKernelGGL((sart_bp_kernel<VT, true>), grid, dim3(256), sh.lds, st, L);
-    else if (sart)
-        hipLaunchKernelGGL((sart_bp_kernel<VT, false>), grid, dim3(256), sh.lds, st, L);
-    else if (sh.part)
-        hipLaunchKernelGGL((bp_kernel<VT, PT, true>), grid, dim3(256), sh.lds, st, L);
-    else
-        hipLaunchKernelGGL((bp_kernel<VT, PT, false>), grid, dim3(256), sh.lds, st, L);
+#define CYL_BP_LAUNCH(PART, SBB)                                                                      \
+    do {                                                                                              \
+        if (sart)                                                                                     \
+            hipLaunchKernelGGL((sart_bp_kernel<VT, PART, SBB>), grid, dim3(64 * SBB), sh.lds, st, L); \
+        else                                                                                          \
+            hipLaunchKernelGGL((bp_kernel<VT, PT, PART, SBB>), grid, dim3(64 * SBB), sh.lds, st, L);  \
+    } while (0)
+    if (sh.sbb == 8) {
+        if (sh.part)
+            CYL_BP_LAUNCH(true, 8);
+        else
+            CYL_BP_LAUNCH(false, 8);
+    } else {
+        if (sh.part)
+            CYL_BP_LAUNCH(true, 4);
+        else
+            CYL_BP_LAUNCH(false, 4);
+    }
+#undef CYL_BP_LAUNCH
 }
 
 template <int VT>
@@ -1581,16 +1608,29 @@ static void launch_bp_v(const BpLaunch &L, const LaunchShape &sh, int pt, bool s
 
 static void launch_bp_batch(const BpLaunch &L, const cyl_geom *const *geoms, int vt, int pt, bool sart,
                             hipStream_t st) {
-    LaunchShape sh;
-    for (int i = 0; i < L.n; ++i) {
-        sh.maxwg = std::max(sh.maxwg, L.item[i].nwg);
-        sh.part = sh.part || bp_lds_bytes(geoms[i]->dev, false) > kLdsFor4;
-    }
-    for (int i = 0; i < L.n; ++i) sh.lds = std::max(sh.lds, bp_lds_bytes(geoms[i]->dev, sh.part));
-    switch (vt) {
-        case CYL_F32: launch_bp_v<CYL_F32>(L, sh, pt, sart, st); break;
-        case CYL_F16: launch_bp_v<CYL_F16>(L, sh, pt, sart, st); break;
-        default: launch_bp_v<CYL_BF16>(L, sh, pt, sart, st); break;
+    for (int sbb = 8; sbb >= 4; sbb /= 2) {  // one launch per super-block size
+        LaunchShape sh;
+        sh.sbb = sbb;
+        BpLaunch L2;
+        L2.n = 0;
+        const cyl_geom *g2[kMaxBatch];
+        for (int i = 0; i < L.n; ++i) {
+            if (grid_sbb(geoms[i]->dev) != sbb) continue;
+            BpItem it = L.item[i];
+            const SbShape sb = sb_shape(it.g, sbb);
+            it.nwg = sb.nsr * sb.nst * sb.nsh;
+            g2[L2.n] = geoms[i];
+            L2.item[L2.n++] = it;
+            sh.maxwg = std::max(sh.maxwg, it.nwg);
+            sh.part = sh.part || bp_lds_bytes(geoms[i]->dev, false, sbb) > lds_for_4(sbb);
+        }
+        if (L2.n == 0) continue;
+        for (int i = 0; i < L2.n; ++i) sh.lds = std::max(sh.lds, bp_lds_bytes(g2[i]->dev, sh.part, sbb));
+        switch (vt) {
+            case CYL_F32: launch_bp_v<CYL_F32>(L2, sh, pt, sart, st); break;
+            case CYL_F16: launch_bp_v<CYL_F16>(L2, sh, pt, sart, st); break;
+            default: launch_bp_v<CYL_BF16>(L2, sh, pt, sart, st); break;
+        }
     }
 }
 
