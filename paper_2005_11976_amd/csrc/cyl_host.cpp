@@ -331,25 +331,10 @@ extern "C" int cyl_geom_create(const cyl_grid *grid, const cyl_traj *traj, const
     if (bt < 1) bt = 1;
     if (bt > 16) bt = 16;
     d.bt = bt;
-    // tuning override "bh,bt,br" (cells per block), used by block-shape sweeps
-    if (const char *env = getenv("CYL_BP_BLOCK")) {
-        int a = 0, b = 0, c = 0;
-        if (sscanf(env, "%d,%d,%d", &a, &b, &c) == 3 && a >= 1 && b >= 1 && c >= 1 &&
-            a * b * c <= kBlockCells) {
-            d.bh = a < g.n_h ? a : g.n_h;
-            d.bt = b < g.n_theta / 2 ? b : (g.n_theta / 2 > 0 ? g.n_theta / 2 : 1);
-            d.br = c < g.n_r ? c : g.n_r;
-        }
-    }
-    // shrink the block until 4 accumulator blocks (c and n) fit beside the tables
-    while ((size_t)4 * 2 * 4 * (d.bh * (d.bt * (d.br + 1) + 1) + 1) + table_bytes > kMaxLds) {
-        if (d.br > 4)
-            d.br /= 2;
-        else if (d.bt > 1)
-            d.bt = (d.bt + 1) / 2;
-        else
-            d.bh = 1;
-    }
+    // The back-projection needs at most 8 accumulator blocks of 64-bit words
+    // (8 x 1093 x 8 bytes for 4 x 16 x 16 blocks) beside at most the sector-edge
+    // table (a part of it when the whole would crowd the CU): well inside the
+    // 160 KiB a workgroup may hold, so the block shape does not depend on N_theta.
     d.nbh = (g.n_h + d.bh - 1) / d.bh;
     d.nbt = (g.n_theta + d.bt - 1) / d.bt;
     d.nbr = (g.n_r + d.br - 1) / d.br;

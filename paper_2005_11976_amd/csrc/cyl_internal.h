@@ -42,8 +42,7 @@ struct GeomDev {
     int32_t nbh, nbt, nbr;
 };
 
-constexpr int kBlockCells = 1024;    // max cells per back-projection block (one block per wave)
-constexpr size_t kMaxLds = 65536;    // LDS per workgroup: grid tables + 4 block accumulators
+constexpr size_t kMaxLds = 65536;    // grid tables (staged in LDS) are limited to kMaxLds / 2 bytes
 
 }  // namespace cyl
 
