@@ -1452,9 +1452,10 @@ static FpItem fp_item(const cyl_geom *G, const void *vol, void *proj, int view, 
     return it;
 }
 
+// One back-projection item; its workgroup count is set by launch_bp_batch,
+// which picks the super-block size.
 static BpItem bp_item(const cyl_geom *G, const void *y, int vb, int ve, void *vol, int accumulate, const void *vw,
-                      int vwt, float lam, int nonneg, bool sart, const int32_t *views = nullptr) {
-    const GeomDev &g = G->dev;
+                      int vwt, float lam, int nonneg, const int32_t *views = nullptr) {
     BpItem it;
     it.g = G->dev;
     it.y = y;
@@ -1463,9 +1464,7 @@ static BpItem bp_item(const cyl_geom *G, const void *y, int vb, int ve, void *vo
     it.views = views;
     it.view_begin = vb;
     it.view_end = ve;
-    it.nwg = 0;  // set with the launch's super-block size (launch_bp_batch)
-    (void)sart;
-    (void)g;
+    it.nwg = 0;
     it.flags = (accumulate ? 1 : 0) | (nonneg ? 2 : 0) | (vwt << 8);
     it.lam = lam;
     return it;
@@ -1642,7 +1641,7 @@ static void launch_bp(const cyl_geom *G, const void *y, int pt, int vb, int ve, 
                       const int32_t *views = nullptr) {
     BpLaunch L;
     L.n = 1;
-    L.item[0] = bp_item(G, sart ? (const void *)rho : y, vb, ve, vol, accumulate, vw, vwt, lam, nonneg, sart, views);
+    L.item[0] = bp_item(G, sart ? (const void *)rho : y, vb, ve, vol, accumulate, vw, vwt, lam, nonneg, views);
     const cyl_geom *geoms[1] = {G};
     launch_bp_batch(L, geoms, vt, pt, sart, st);
 }
@@ -1993,7 +1992,7 @@ extern "C" int cyl_sart_batch_step(int32_t n, const cyl_sart_batch_item *items, 
         for (int i = 0; i < L.n; ++i) {
             const cyl_sart_batch_item &it = items[i0 + i];
             L.item[i] = bp_item(it.geom, it.workspace, it.view, it.view + 1, it.vol, 0, it.vox_weights, vwt,
-                                (float)it.lambda, it.nonneg, true);
+                                (float)it.lambda, it.nonneg);
             geoms[i] = it.geom;
         }
         launch_bp_batch(L, geoms, vt, CYL_F32, true, st);
