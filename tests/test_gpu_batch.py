@@ -112,6 +112,29 @@ def test_batch_matches_alone_bitwise(torch_cuda, dtype_name):
         assert np.array_equal(got, a), j.name
 
 
+def test_batch_mixing_super_block_sizes_matches_alone_bitwise(torch_cuda):
+    """A grid just above 2^25 cells (back-projected on 4-block super-blocks)
+    batched with small grids (8-block super-blocks): the step launches each
+    size separately, and every scan's result is bitwise its result alone."""
+    torch = torch_cuda
+    big = I.Scan(I.Grid(64, 1024, 513, 0.0, 10.0, -5.0, 5.0),
+                 I.circular_views(3, 100.0, 200.0, 0.8, phi0=0.21), 20, 28, np.eye(3), np.zeros(3))
+    assert big.grid.n_vox > 1 << 25
+    scans = [("big", big), ("scaled_posed", _scans()[1][1]), ("tiny", _scans()[0][1])]
+    jobs = [_Job(torch, n, s, 1400 + i, torch.float32, 1) for i, (n, s) in enumerate(scans)]
+    alone = []
+    for j in jobs:
+        say("alone", j.name)
+        alone.append(host(_alone(torch, j)))
+    say("batched, mixed super-block sizes")
+    _batched(jobs, 13)
+    for j, a in zip(jobs, alone):
+        got = host(j.vol)
+        say("mixed batch vs alone", j.name, "max |diff| %.3g" % float(np.max(np.abs(got - a))))
+        assert np.array_equal(got, a), j.name
+        assert not np.array_equal(got, j.prior_host.astype(np.float32)), j.name  # updated
+
+
 def test_batch_of_more_than_16_and_oracle(torch_cuda):
     """18 tiny scans in one step call (two launches of 16 and 2), one step per
     view for one iteration; every result against the FP64 oracle's SART."""
