@@ -229,6 +229,35 @@ def test_single_scan_full_size_bp_one_view(torch_cuda):
     _fp_bp_check(torch_cuda, scan, 17, 18, 4021, "single posed view 17")
 
 
+def test_single_scan_full_size_bp_all_views_is_sum_of_views(torch_cuda):
+    """256x720x128, 120 views: cyl_bp over all views in one call (one
+    fixed-point scale per super-block for all of them) equals the sum of the
+    120 one-view calls (each the one-view transpose checked against the
+    oracle above), within 1e-6; and the FP of the whole scan in one call
+    (one ray per lane) equals one-view calls (rays split over 4 lanes), within
+    1e-6."""
+    torch = torch_cuda
+    cfg = I.config_single()
+    scan = cfg["scan"]
+    G = _geom(scan)
+    y = dev(I.uniform_vector(scan.n_views * scan.det_rows * scan.det_cols, 4060).astype(np.float32)
+            .reshape(scan.proj_shape))
+    say("full bp all views")
+    whole = host(G.bp(y))
+    acc = dev(np.zeros(scan.grid.shape, np.float32))
+    for k in range(scan.n_views):
+        G.bp(y, acc, view_begin=k, view_end=k + 1, accumulate=True)
+    e = rel_l2(whole, host(acc).astype(np.float64))
+    say("full bp all views vs sum of one-view calls: rel L2 %.2e" % e)
+    assert e <= 1e-6
+    x = dev(I.uniform_vector(scan.grid.n_vox, 4061).astype(np.float32).reshape(scan.grid.shape))
+    q = host(G.fp(x))
+    q1 = np.stack([host(G.fp(x, view_begin=k, view_end=k + 1))[k] for k in range(0, scan.n_views, 17)])
+    e = rel_l2(q[::17], q1.astype(np.float64))
+    say("full fp all views vs one-view calls: rel L2 %.2e" % e)
+    assert e <= 1e-6
+
+
 def test_posed_large_bp_one_view(torch_cuda):
     """512x1440x256 posed scan, 1024x768 detector: one view FP and BP."""
     cfg = I.config_posed()
