@@ -392,6 +392,37 @@ def test_sart_ragged_detector(torch_cuda, subset):
     assert rel_l2(mu, ph.prior) > 1e-3  # the updates are not trivial
 
 
+def test_fine_sectors_partial_edge_table(torch_cuda):
+    """A small grid with 1600 sectors (4 x 1600 x 16): its whole sector-edge
+    table would crowd the CU, so the back-projection stages only each
+    super-block's edges (8-block super-blocks, grid below 2^25 cells).  FP and
+    the plain transpose against the oracle (with the adjoint identity), and
+    weighted SART for 2 iterations."""
+    grid = I.Grid(4, 1600, 16, 1.0, 6.0, -2.0, 2.0, 0.01)
+    R, T = I.pose_from(0.3, 0.08, 0.7, [0.2, -0.1, 0.05])
+    scan = I.Scan(grid, I.circular_views(4, 40.0, 80.0, 0.5, phi0=0.13), 10, 30, R, T)
+    _fp_bp_check(torch_cuda, scan, 0, 4, 4070, "fine sectors")
+    rng = np.random.default_rng(4071)
+    truth = rng.uniform(0.0, 1.0, size=grid.shape)
+    prior = truth * rng.uniform(0.8, 1.2, size=grid.shape)
+    wv = rng.uniform(0.25, 1.0, size=grid.shape)
+    o = ref.Oracle(scan)
+    p = o.fp(truth)
+    G = _geom(scan)
+    pg, wg = dev(p.astype(np.float32)), dev(wv.astype(np.float32))
+    vol = dev(prior.astype(np.float32))
+    mu = prior.astype(np.float32).astype(np.float64)
+    for it in range(2):
+        say("fine sectors sart iteration", it)
+        G.sart(pg, vol, it + 1, 0.5, vox_weights=wg, start_iter=it)
+        mu, _ = o.sart(p.astype(np.float32).astype(np.float64), mu, it + 1, 0.5, vox_weights=wv.astype(np.float32),
+                       start_iter=it)
+        e = rel_l2(host(vol), mu)
+        say("fine sectors sart iteration %d rel L2 %.2e" % (it, e))
+        assert e <= 1e-4
+    assert rel_l2(mu, prior) > 1e-3
+
+
 def test_sart_invariants_bitwise(torch_cuda):
     torch = torch_cuda
     scan = I.scaled_single(n_h=16, n_theta=48, n_r=12, n_views=8, det=40, posed_seed=2007)
