@@ -1415,13 +1415,20 @@ static size_t bp_lds_bytes(const GeomDev &g, bool part, int sbb) {
 // 160 KiB.
 static size_t lds_for_4(int sbb) { return (size_t)160 * 1024 * sbb / 16; }
 
-// Blocks per super-block of a grid: 8 up to 2^25 cells, else 4 (measured: 8
-// took the 256x720x128 update from 0.403 to 0.388 ms per view, unposed and
-// posed alike, and 4 kept the 512x1440x256 posed one at 3.05 ms against 3.61).
-// A property of the grid alone, so a scan's result does not depend on the
-// batch it is launched with; a launch holds items of one size.
+// Blocks per super-block of a grid: 8 when the grid has at most 2^25 cells,
+// stages the whole sector-edge table and still gives at least 8 super-blocks
+// per CU (2048); else 4.  Measured per view: 8 took the 256x720x128 update
+// (2944 super-blocks) from 0.403 to 0.388 ms, unposed and posed alike; 4 kept
+// the 512x1440x256 posed one at 3.05 ms against 3.61, the 32x512x256 one
+// (512 super-blocks) at 0.295 against 0.333 and the 32x1608x256 one (partial
+// table) at 0.479 against 0.485.  A property of the grid alone, so a scan's
+// result does not depend on the batch it is launched with; a launch holds
+// items of one size, and only 4-block launches stage partial tables.
 static int grid_sbb(const GeomDev &g) {
-    return (int64_t)g.n_h * g.n_theta * g.n_r > ((int64_t)1 << 25) ? 4 : 8;
+    if ((int64_t)g.n_h * g.n_theta * g.n_r > ((int64_t)1 << 25)) return 4;
+    if (bp_lds_bytes(g, false, 8) > lds_for_4(8)) return 4;
+    const SbShape sb = sb_shape(g, 8);
+    return (int64_t)sb.nsh * sb.nst * sb.nsr >= 2048 ? 8 : 4;
 }
 
 // Rays per item below which each ray is split over neighbouring lanes so one
@@ -1579,10 +1586,7 @@ static void launch_bp_t(const BpLaunch &L, const LaunchShape &sh, bool sart, hip
             hipLaunchKernelGGL((bp_kernel<VT, PT, PART, SBB>), grid, dim3(64 * SBB), sh.lds, st, L);  \
     } while (0)
     if (sh.sbb == 8) {
-        if (sh.part)
-            CYL_BP_LAUNCH(true, 8);
-        else
-            CYL_BP_LAUNCH(false, 8);
+        CYL_BP_LAUNCH(false, 8);
     } else {
         if (sh.part)
             CYL_BP_LAUNCH(true, 4);
@@ -1621,7 +1625,7 @@ static void launch_bp_batch(const BpLaunch &L, const cyl_geom *const *geoms, int
             g2[L2.n] = geoms[i];
             L2.item[L2.n++] = it;
             sh.maxwg = std::max(sh.maxwg, it.nwg);
-            sh.part = sh.part || bp_lds_bytes(geoms[i]->dev, false, sbb) > lds_for_4(sbb);
+            sh.part = sh.part || bp_lds_bytes(geoms[i]->dev, false, sbb) > lds_for_4(sbb);  // never for 8
         }
         if (L2.n == 0) continue;
         for (int i = 0; i < L2.n; ++i) sh.lds = std::max(sh.lds, bp_lds_bytes(g2[i]->dev, sh.part, sbb));

@@ -113,14 +113,17 @@ def test_batch_matches_alone_bitwise(torch_cuda, dtype_name):
 
 
 def test_batch_mixing_super_block_sizes_matches_alone_bitwise(torch_cuda):
-    """A grid just above 2^25 cells (back-projected on 4-block super-blocks)
-    batched with small grids (8-block super-blocks): the step launches each
-    size separately, and every scan's result is bitwise its result alone."""
+    """A grid just above 2^25 cells and two small ones (back-projected on
+    4-block super-blocks) batched with a 128 x 1024 x 128 grid (8-block
+    super-blocks: the whole sector-edge table fits and it has 2048 of them):
+    the step launches each size separately, and every scan's result is
+    bitwise its result alone."""
     torch = torch_cuda
-    big = I.Scan(I.Grid(64, 1024, 513, 0.0, 10.0, -5.0, 5.0),
-                 I.circular_views(3, 100.0, 200.0, 0.8, phi0=0.21), 20, 28, np.eye(3), np.zeros(3))
+    views = I.circular_views(3, 100.0, 200.0, 0.8, phi0=0.21)
+    big = I.Scan(I.Grid(64, 1024, 513, 0.0, 10.0, -5.0, 5.0), views, 20, 28, np.eye(3), np.zeros(3))
     assert big.grid.n_vox > 1 << 25
-    scans = [("big", big), ("scaled_posed", _scans()[1][1]), ("tiny", _scans()[0][1])]
+    mid = I.Scan(I.Grid(128, 1024, 128, 0.0, 10.0, -5.0, 5.0), views, 20, 28, np.eye(3), np.zeros(3))
+    scans = [("big", big), ("mid", mid), ("scaled_posed", _scans()[1][1]), ("tiny", _scans()[0][1])]
     jobs = [_Job(torch, n, s, 1400 + i, torch.float32, 1) for i, (n, s) in enumerate(scans)]
     alone = []
     for j in jobs:

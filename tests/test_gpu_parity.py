@@ -395,7 +395,8 @@ def test_sart_ragged_detector(torch_cuda, subset):
 def test_fine_sectors_partial_edge_table(torch_cuda):
     """A small grid with 1600 sectors (4 x 1600 x 16): its whole sector-edge
     table would crowd the CU, so the back-projection stages only each
-    super-block's edges (8-block super-blocks, grid below 2^25 cells).  FP and
+    super-block's edges (on 4-block super-blocks, the only ones that stage a
+    part of the table).  FP and
     the plain transpose against the oracle (with the adjoint identity), and
     weighted SART for 2 iterations."""
     grid = I.Grid(4, 1600, 16, 1.0, 6.0, -2.0, 2.0, 0.01)
