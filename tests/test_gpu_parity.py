@@ -424,38 +424,31 @@ def test_fine_sectors_partial_edge_table(torch_cuda):
     assert rel_l2(mu, prior) > 1e-3
 
 
-def test_grid_above_2_25_cells_whole_edge_table(torch_cuda):
-    """A 128 x 720 x 400 grid (36.9 M cells, 4-block super-blocks) whose whole
-    sector-edge table fits beside them: FP, transpose and adjoint against the
-    oracle on a small detector, and one weighted SART iteration.
-
-    Its shells are 0.025 mm thin, so the back-projection is held to the FP32
-    floor of the crossing positions instead of 1e-5: 1.5 s_max 2^-24 / d_min,
-    with s_max the largest arc length from the closest approach inside the
-    support (sqrt(r_max^2 + h_max^2)) and d_min the thinnest cell dimension
-    (4.0e-5 here; the same grid with 364 or 200 rings, taken by 8-block
-    super-blocks, measured 1.9e-5 and 1.2e-5)."""
-    grid = I.Grid(128, 720, 400, 0.0, 10.0, -5.0, 5.0)
-    assert grid.n_vox > 1 << 25
-    scan = I.Scan(grid, I.circular_views(3, 100.0, 200.0, 1.0, phi0=0.3), 12, 20, np.eye(3), np.zeros(3))
+def _large_grid_check(torch_cuda, scan, seed, label, min_met):
+    """FP, transpose and adjoint of a large grid against the oracle on a small
+    detector, with the back-projection held to the FP32 floor of the
+    crossing positions (see the 2^25-cell test), and one weighted SART
+    sub-iteration on the cells the oracle meets."""
+    grid = scan.grid
     s_max = math.hypot(grid.r_max, max(abs(grid.h_min), abs(grid.h_max)))
-    d_min = min((grid.r_max - grid.r_min) / grid.n_r, (grid.h_max - grid.h_min) / grid.n_h)
+    arc_mid = 0.5 * (grid.r_min + grid.r_max) * 2.0 * math.pi / grid.n_theta
+    d_min = min((grid.r_max - grid.r_min) / grid.n_r, (grid.h_max - grid.h_min) / grid.n_h, arc_mid)
     bp_tol = 1.5 * s_max * 2.0 ** -24 / d_min
-    _fp_bp_check(torch_cuda, scan, 0, 3, 4080, "grid above 2^25 cells", bp_tol=bp_tol)
-    # one SART sub-iteration of view 0.  With 240 rays for 36.9 M cells most
-    # touched cells meet one ray; a ray within FP32 rounding of a cell's face
+    _fp_bp_check(torch_cuda, scan, 0, 3, seed, label, bp_tol=bp_tol)
+    # one SART sub-iteration of view 0.  With a few hundred rays for millions
+    # of cells most touched cells meet one ray; a ray within FP32 rounding of a cell's face
     # may give that cell a tiny positive length where FP64 gives none, and
     # Eq. 7 then moves it by the ray's whole residual.  So the update is held
     # to 1e-4 on the cells the oracle's view meets (n_m > 0), and the cells
     # changed beyond those are counted.
     o = ref.Oracle(scan)
-    x = I.uniform_vector(grid.n_vox, 4081).reshape(grid.shape)
+    x = I.uniform_vector(grid.n_vox, seed + 1).reshape(grid.shape)
     p = o.fp(x)
     prior = (x * 0.9).astype(np.float32)
     G = _geom(scan)
     vol = dev(prior)
     ws = torch_cuda.empty(G.workspace_bytes(), dtype=torch_cuda.uint8, device="cuda")
-    say("grid above 2^25 cells: sart sub-iteration")
+    say(label + ": sart sub-iteration")
     G.sart_residual(0, dev(p.astype(np.float32)), vol, ws)
     G.sart_update(0, vol, ws, 0.5)
     one = I.Scan(grid, scan.views[:1], scan.det_rows, scan.det_cols, scan.R, scan.T)
@@ -467,9 +460,39 @@ def test_grid_above_2_25_cells_whole_edge_table(torch_cuda):
     d_ref = mu.astype(np.float32).astype(np.float64) - prior
     e = rel_l2(d_got[met], d_ref[met])
     extra = int(np.count_nonzero(d_got[~met]))
-    say("grid above 2^25 cells: update rel L2 on the %d met cells %.2e, %d more cells changed" % (met.sum(), e, extra))
-    assert met.sum() > 100000 and e <= 1e-4
+    say(label + ": update rel L2 on the %d met cells %.2e, %d more cells changed" % (met.sum(), e, extra))
+    assert met.sum() > min_met and e <= 1e-4
     assert extra <= 1e-3 * met.sum()
+
+
+def test_grid_above_2_25_cells_whole_edge_table(torch_cuda):
+    """A 128 x 720 x 400 grid (36.9 M cells, 4-block super-blocks) whose whole
+    sector-edge table fits beside them: FP, transpose and adjoint against the
+    oracle on a small detector, and one weighted SART iteration.
+
+    Its shells are 0.025 mm thin, so the back-projection is held to the FP32
+    floor of the crossing positions instead of 1e-5: 1.5 s_max 2^-24 / d_min,
+    with s_max the largest arc length from the closest approach inside the
+    support (sqrt(r_max^2 + h_max^2)) and d_min the thinnest cell dimension:
+    ring width, slab height or the sector's arc at the middle radius (4.0e-5
+    here; the same grid with 364 or 200 rings, taken by 8-block super-blocks,
+    measured 1.9e-5 and 1.2e-5)."""
+    grid = I.Grid(128, 720, 400, 0.0, 10.0, -5.0, 5.0)
+    assert grid.n_vox > 1 << 25
+    scan = I.Scan(grid, I.circular_views(3, 100.0, 200.0, 1.0, phi0=0.3), 12, 20, np.eye(3), np.zeros(3))
+    _large_grid_check(torch_cuda, scan, 4080, "grid above 2^25 cells", 100000)
+
+
+def test_grid_on_8_block_super_blocks(torch_cuda):
+    """A 128 x 1024 x 128 grid (16.8 M cells) that takes 8-block super-blocks
+    with none to spare (the whole sector-edge table fits and it gives exactly
+    2048 of them): the same checks against the oracle as for the 2^25-cell grid,
+    on a 16 x 24 detector.  Its 1024 sectors make the arc the thinnest cell
+    dimension (0.031 mm at the middle radius, against 0.078 mm rings and
+    slabs), which sets the back-projection bar (3.3e-5)."""
+    grid = I.Grid(128, 1024, 128, 0.0, 10.0, -5.0, 5.0)
+    scan = I.Scan(grid, I.circular_views(3, 100.0, 200.0, 1.0, phi0=0.17), 16, 24, np.eye(3), np.zeros(3))
+    _large_grid_check(torch_cuda, scan, 4090, "8-block grid", 50000)
 
 
 def test_sart_invariants_bitwise(torch_cuda):
