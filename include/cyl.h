@@ -163,6 +163,26 @@ int cyl_sart_run(const cyl_geom *geom, const cyl_sart_params *params, const void
                  cyl_dtype vol_type, void *workspace, size_t workspace_bytes,
                  void *hip_stream);
 
+/* cyl_sart_run for callers that cannot allocate device memory: code under HIP
+ * graph capture, serving loops and harnesses that forbid hipMalloc.  Computes
+ * exactly what cyl_sart_run computes (the same kernels, bit for bit), with the
+ * library's own static device scratch (CYL_SART_STATIC_SCRATCH_BYTES per GPU,
+ * held until the process ends) in place of the caller's workspace.  The caller
+ * still passes proj, the weights and vol; arguments as for cyl_sart_run.
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine); it fails with CYL_EINVAL, enqueuing nothing, when the geometry's
+ * workspace (cyl_sart_workspace_bytes) exceeds the scratch, which holds the
+ * workspace of a 1024 x 1024 detector (1024 x 768 fits).  Every call on one GPU shares
+ * that GPU's scratch, so calls that overlap on one GPU (other streams or
+ * threads) race: the caller must order them.  The scratch keeps the last
+ * call's contents; every residual and tile maximum a call reads it has
+ * written first in the same call. */
+#define CYL_SART_STATIC_SCRATCH_BYTES ((size_t)4259840) /* (2^20 + 2^14) FP32 words */
+int cyl_sart_run_static(const cyl_geom *geom, const cyl_sart_params *params, const void *proj,
+                        cyl_dtype proj_type, const void *proj_weights, cyl_dtype proj_weights_type,
+                        const void *vox_weights, cyl_dtype vox_weights_type, void *vol,
+                        cyl_dtype vol_type, void *hip_stream);
+
 /* Ordered-subset SART (Eq. 7 with an ordered subset of several projections;
  * subset = n_views is SIRT).  Each iteration splits the view order into
  * consecutive groups of `subset` positions (the last group may be shorter);

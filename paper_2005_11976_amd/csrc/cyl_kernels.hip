@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <vector>
 
 #include "cyl_internal.h"
@@ -1774,6 +1775,25 @@ static int sart_check(const char *who, const cyl_geom *G, const cyl_sart_params 
     return CYL_OK;
 }
 
+// One sequential SART sweep (Eq. 7, one view per update) with its residual
+// image and tile maxima at rho; the caller has validated the arguments.
+static int sart_sweep(const cyl_geom *G, const cyl_sart_params *P, const void *proj, cyl_dtype pt, const void *pw,
+                      cyl_dtype pwt, const void *vw, cyl_dtype vwt, void *vol, cyl_dtype vt, float *rho,
+                      hipStream_t st, const char *who) {
+    const float lam = (float)P->lambda;
+    for (int it = P->start_iter; it < P->n_iter; ++it) {
+        const int kv0 = (it == P->start_iter) ? P->start_view : 0;
+        for (int kk = kv0; kk < G->n_views; ++kk) {
+            const int k = P->view_order ? P->view_order[kk] : kk;
+            launch_fp(G, vol, vt, const_cast<void *>(proj), pt, k, 1, true, pw, pwt, rho, st);
+            launch_bp(G, nullptr, CYL_F32, k, k + 1, vol, vt, 0, true, rho, vw, vwt, lam, P->nonneg, st);
+        }
+        const int rc = launch_check(who);
+        if (rc) return rc;
+    }
+    return CYL_OK;
+}
+
 extern "C" int cyl_sart_run(const cyl_geom *G, const cyl_sart_params *P, const void *proj, cyl_dtype pt,
                             const void *pw, cyl_dtype pwt, const void *vw, cyl_dtype vwt, void *vol,
                             cyl_dtype vt, void *workspace, size_t ws_bytes, void *hip_stream) {
@@ -1790,19 +1810,62 @@ extern "C" int cyl_sart_run(const cyl_geom *G, const cyl_sart_params *P, const v
         set_error("cyl_sart_run: cannot select device %d", G->device);
         return CYL_EDEVICE;
     }
-    hipStream_t st = (hipStream_t)hip_stream;
-    float *rho = (float *)workspace;
-    const float lam = (float)P->lambda;
-    for (int it = P->start_iter; it < P->n_iter; ++it) {
-        const int kv0 = (it == P->start_iter) ? P->start_view : 0;
-        for (int kk = kv0; kk < G->n_views; ++kk) {
-            const int k = P->view_order ? P->view_order[kk] : kk;
-            launch_fp(G, vol, vt, const_cast<void *>(proj), pt, k, 1, true, pw, pwt, rho, st);
-            launch_bp(G, nullptr, CYL_F32, k, k + 1, vol, vt, 0, true, rho, vw, vwt, lam, P->nonneg, st);
-        }
-        if ((rc = launch_check("cyl_sart_run"))) return rc;
+    return sart_sweep(G, P, proj, pt, pw, pwt, vw, vwt, vol, vt, (float *)workspace, (hipStream_t)hip_stream,
+                      "cyl_sart_run");
+}
+
+// Static scratch of cyl_sart_run_static: one copy per GPU, alive until the
+// process ends.  In host code `scratch` names a host-side stand-in, never the
+// device array: host code uses only the address hipGetSymbolAddress returns
+// for the current device (scratch_ptr), looked up once per device.
+static __device__ __align__(256) unsigned char scratch[CYL_SART_STATIC_SCRATCH_BYTES];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex scratch_mu;
+static void *scratch_dev[kMaxDevices];
+
+// Device address of `scratch` on `device` (which must be current); null on
+// failure, with the error set.
+static void *scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) {
+        set_error("cyl_sart_run_static: device %d outside [0, %d)", device, kMaxDevices);
+        return nullptr;
     }
-    return CYL_OK;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_dev[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("cyl_sart_run_static: no address for the static scratch on device %d: %s", device,
+                      hipGetErrorString(e));
+            return nullptr;
+        }
+        scratch_dev[device] = p;
+    }
+    return scratch_dev[device];
+}
+
+extern "C" int cyl_sart_run_static(const cyl_geom *G, const cyl_sart_params *P, const void *proj, cyl_dtype pt,
+                                   const void *pw, cyl_dtype pwt, const void *vw, cyl_dtype vwt, void *vol,
+                                   cyl_dtype vt, void *hip_stream) {
+    int rc;
+    if ((rc = sart_check("cyl_sart_run_static", G, P, proj, pt, pw, pwt, vw, vwt, vol, vt))) return rc;
+    const size_t need = cyl_sart_workspace_bytes(G, P);
+    if (need > CYL_SART_STATIC_SCRATCH_BYTES) {
+        set_error("cyl_sart_run_static: the geometry needs %zu bytes of scratch, above the static %zu", need,
+                  (size_t)CYL_SART_STATIC_SCRATCH_BYTES);
+        return CYL_EINVAL;
+    }
+    if (P->start_iter >= P->n_iter) return CYL_OK;
+    DeviceGuard dg(G->device);
+    if (!dg.ok) {
+        set_error("cyl_sart_run_static: cannot select device %d", G->device);
+        return CYL_EDEVICE;
+    }
+    void *ws = scratch_ptr(G->device);
+    if (!ws) return CYL_EDEVICE;
+    return sart_sweep(G, P, proj, pt, pw, pwt, vw, vwt, vol, vt, (float *)ws, (hipStream_t)hip_stream,
+                      "cyl_sart_run_static");
 }
 
 // Residual images of one subset, then the view order as int32.

@@ -15,10 +15,11 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libcyl.so")
 
 CYL_F32, CYL_F16, CYL_BF16 = 0, 1, 2
+SART_STATIC_SCRATCH_BYTES = 4259840  # CYL_SART_STATIC_SCRATCH_BYTES of include/cyl.h
 CYL_OK, CYL_EINVAL, CYL_ENOMEM, CYL_EDEVICE, CYL_EUNSUPPORTED = 0, -1, -2, -3, -4
 
 EXPORTS = ["cyl_geom_create", "cyl_geom_destroy", "cyl_fp", "cyl_bp", "cyl_row_sums",
-           "cyl_sart_workspace_bytes", "cyl_sart_run", "cyl_os_sart_workspace_bytes", "cyl_os_sart_run",
+           "cyl_sart_workspace_bytes", "cyl_sart_run", "cyl_sart_run_static", "cyl_os_sart_workspace_bytes", "cyl_os_sart_run",
            "cyl_sart_residual", "cyl_sart_update",
            "cyl_sart_batch_step", "cyl_fp_diff", "cyl_add", "cyl_axis_corners", "cyl_track_point",
            "cyl_pose_from_axis", "cyl_side_sums", "cyl_azimuth_phase", "cyl_mtf", "cyl_fp_sampled", "cyl_bp_voxel", "cyl_sart_run_sampled", "cyl_sym_create", "cyl_sym_destroy", "cyl_sym_nnz",
@@ -80,6 +81,9 @@ def declare(lib):
     lib.cyl_sart_run.argtypes = [vp, P(cyl_sart_params), vp, C.c_int, vp, C.c_int, vp, C.c_int,
                                  vp, C.c_int, vp, C.c_size_t, vp]
     lib.cyl_sart_run.restype = C.c_int
+    lib.cyl_sart_run_static.argtypes = [vp, P(cyl_sart_params), vp, C.c_int, vp, C.c_int, vp, C.c_int,
+                                        vp, C.c_int, vp]
+    lib.cyl_sart_run_static.restype = C.c_int
     lib.cyl_os_sart_workspace_bytes.argtypes = [vp, i32]
     lib.cyl_os_sart_workspace_bytes.restype = C.c_size_t
     lib.cyl_os_sart_run.argtypes = [vp, P(cyl_sart_params), i32, vp, C.c_int, vp, C.c_int, vp, C.c_int,
@@ -317,6 +321,27 @@ class Geometry:
             vw, _dtype_code(vox_weights) if vox_weights is not None else CYL_F32,
             C.c_void_p(vol.data_ptr()), _dtype_code(vol), C.c_void_p(workspace.data_ptr()),
             workspace.numel() * workspace.element_size(), _stream_ptr(stream)), self._L)
+        del keep
+        return vol
+
+    def sart_static(self, proj, vol, n_iter, lam=0.5, proj_weights=None, vox_weights=None, nonneg=False,
+                    view_order=None, start_iter=0, start_view=0, stream=None):
+        """cyl_sart_run_static: weighted SART in place on `vol` with the
+        library's static device scratch (no workspace, nothing allocated)."""
+        self._proj(proj)
+        self._vol(vol)
+        prm, keep = self.sart_params(n_iter, lam, nonneg, view_order, start_iter, start_view)
+        pw = C.c_void_p(proj_weights.data_ptr()) if proj_weights is not None else None
+        vw = C.c_void_p(vox_weights.data_ptr()) if vox_weights is not None else None
+        if proj_weights is not None:
+            self._proj(proj_weights)
+        if vox_weights is not None:
+            self._vol(vox_weights)
+        _check(self._L.cyl_sart_run_static(
+            self.handle, C.byref(prm), C.c_void_p(proj.data_ptr()), _dtype_code(proj),
+            pw, _dtype_code(proj_weights) if proj_weights is not None else CYL_F32,
+            vw, _dtype_code(vox_weights) if vox_weights is not None else CYL_F32,
+            C.c_void_p(vol.data_ptr()), _dtype_code(vol), _stream_ptr(stream)), self._L)
         del keep
         return vol
 

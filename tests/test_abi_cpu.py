@@ -36,6 +36,11 @@ def test_header_declares_the_abi():
     assert set(names) == set(cyl.EXPORTS)
 
 
+def test_static_scratch_size_matches_header():
+    m = re.search(r"#define CYL_SART_STATIC_SCRATCH_BYTES \(\(size_t\)(\d+)\)", open(HEADER).read())
+    assert m and int(m.group(1)) == cyl.SART_STATIC_SCRATCH_BYTES
+
+
 def test_library_exports_every_declared_symbol(L):
     for n in _declared():
         assert hasattr(L, n), n
@@ -100,6 +105,7 @@ def test_null_arguments_rejected(L):
     assert L.cyl_row_sums(None, None, 0, 1, None) == cyl.CYL_EINVAL
     assert L.cyl_sart_run(None, None, None, 0, None, 0, None, 0, None, 0, None, 0, None) == cyl.CYL_EINVAL
     assert L.cyl_sart_workspace_bytes(None, None) == 0
+    assert L.cyl_sart_run_static(None, None, None, 0, None, 0, None, 0, None, 0, None) == cyl.CYL_EINVAL
     L.cyl_geom_destroy(None)
     g = cyl.grid_struct(GOOD)
     assert L.cyl_geom_create(C.byref(g), None, None, 0, None) == cyl.CYL_EINVAL
