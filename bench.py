@@ -45,7 +45,8 @@ VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
 def kernel_src_sha():
     import hashlib
     h = hashlib.sha256()
-    for f in ("cyl_kernels.hip", "cyl_host.cpp", "cyl_internal.h"):
+    for f in ("cyl_kernels.hip", "cyl_host.cpp", "cyl_internal.h", "cyl_ray.h", "cyl_block.h", "cyl_isa.h",
+              "cyl_store.h"):
         with open(os.path.join(ROOT, "paper_2005_11976_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

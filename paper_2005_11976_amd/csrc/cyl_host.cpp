@@ -331,9 +331,9 @@ extern "C" int cyl_geom_create(const cyl_grid *grid, const cyl_traj *traj, const
     if (bt < 1) bt = 1;
     if (bt > 16) bt = 16;
     d.bt = bt;
-    // The back-projection needs at most 8 accumulator blocks of 64-bit words
-    // (8 x 1093 x 8 bytes for 4 x 16 x 16 blocks) beside at most the sector-edge
-    // table (a part of it when the whole would crowd the CU): well inside the
+    // A back-projection super-block of at most 8 such blocks needs at most
+    // 32 (18 x 17 + 1) + 5 64-bit accumulator words (79 KiB, 8 blocks stacked
+    // in h) beside the at most 35 sector edges it stages: well inside the
     // 160 KiB a workgroup may hold, so the block shape does not depend on N_theta.
     d.nbh = (g.n_h + d.bh - 1) / d.bh;
     d.nbt = (g.n_theta + d.bt - 1) / d.bt;

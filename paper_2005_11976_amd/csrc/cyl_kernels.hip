@@ -23,565 +23,45 @@
 #include <vector>
 
 #include "cyl_internal.h"
+#include "cyl_isa.h"
+#include "cyl_block.h"
+#include "cyl_ray.h"
+#include "cyl_store.h"
 
 namespace cyl {
 
-#define CYL_INF __builtin_huge_valf()
-
-// ------------------------------------------------------------ storage types
-
-__device__ __forceinline__ float bf16_to_f32(uint16_t x) { return __uint_as_float((uint32_t)x << 16); }
-
-__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-    u += 0x7fffu + ((u >> 16) & 1u);                                             // nearest even
-    return (uint16_t)(u >> 16);
-}
-
-template <int DT>
-struct Store;
-// ld/st: plain global access.  ldb: load element i through a buffer resource
-// (32-bit offsets, range-checked by the hardware: an offset past the end reads
-// 0), used for the gathers of the traversal.
-template <>
-struct Store<CYL_F32> {
-    static constexpr int kSize = 4;
-    static __device__ __forceinline__ float ld(const void *p, size_t i) { return ((const float *)p)[i]; }
-    static __device__ __forceinline__ void st(void *p, size_t i, float v) { ((float *)p)[i] = v; }
-    static __device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t rs, unsigned i) {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, i << 2, 0, 0));
-    }
-};
-template <>
-struct Store<CYL_F16> {
-    static constexpr int kSize = 2;
-    static __device__ __forceinline__ float ld(const void *p, size_t i) {
-        return __half2float(((const __half *)p)[i]);
-    }
-    static __device__ __forceinline__ void st(void *p, size_t i, float v) {
-        ((__half *)p)[i] = __float2half_rn(v);
-    }
-    static __device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t rs, unsigned i) {
-        const unsigned short x = __builtin_amdgcn_raw_buffer_load_b16(rs, i << 1, 0, 0);
-        return __half2float(__builtin_bit_cast(__half, x));
-    }
-};
-template <>
-struct Store<CYL_BF16> {
-    static constexpr int kSize = 2;
-    static __device__ __forceinline__ float ld(const void *p, size_t i) {
-        return bf16_to_f32(((const uint16_t *)p)[i]);
-    }
-    static __device__ __forceinline__ void st(void *p, size_t i, float v) {
-        ((uint16_t *)p)[i] = f32_to_bf16(v);
-    }
-    static __device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t rs, unsigned i) {
-        return bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(rs, i << 1, 0, 0));
-    }
-};
-
-// Buffer resource over n bytes at p (gfx9 word 3: 32-bit data format).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *p, unsigned nbytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)nbytes, 0x00020000);
-}
-
-// Load of a runtime-typed optional array (weights); the switch is uniform.
-__device__ __forceinline__ float ld_any(const void *p, int dt, size_t i) {
-    if (dt == CYL_F32) return Store<CYL_F32>::ld(p, i);
-    if (dt == CYL_F16) return Store<CYL_F16>::ld(p, i);
-    return Store<CYL_BF16>::ld(p, i);
-}
-
-__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
-
-// min / max of loop-carried values without the canonicalising moves the
-// compiler otherwise inserts before every v_min/v_max (the operands are never
-// signalling NaNs: they come from arithmetic or are +inf)
-__device__ __forceinline__ float vmin3(float a, float b, float c) {
-    float d;
-    asm("v_min3_f32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-    return d;
-}
-__device__ __forceinline__ float vmin(float a, float b) {
-    float d;
-    asm("v_min_f32 %0, %1, %2" : "=v"(d) : "v"(a), "v"(b));
-    return d;
-}
-__device__ __forceinline__ float vmax(float a, float b) {
-    float d;
-    asm("v_max_f32 %0, %1, %2" : "=v"(d) : "v"(a), "v"(b));
-    return d;
-}
-__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
-
-// floor(x + 1/2) as an integer in one instruction (round to nearest, ties
-// upward): the fixed-point sums need a fixed rounding rule, not a particular one.
-__device__ __forceinline__ int round_half_up(float x) {
-    int r;
-    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
-    return r;
-}
-
 // ------------------------------------------------------------ grid tables
 
-// Grid tables as seen by a kernel (staged in LDS by every workgroup).
-struct Tabs {
-    const float2 *r;   // n_r + 1 shell radii (hi, lo)
-    const float2 *h;   // n_h + 1 axial planes (hi, lo)
-    const float2 *cs;  // sector edges cs_lo .. cs_lo + cs_n (cos, sin)
-    int cs_lo, cs_n;
-};
-
-// Sector edge b of a table that may hold only part of the edges (a
-// super-block's wedge).  A walk reads the edge ahead before it checks its
-// box, so on the step that leaves the box b may lie outside the table; that
-// read is clamped to the last entry and its value is never used.
-__device__ __forceinline__ float2 edge_at(const Tabs &T, int b) {
-    return T.cs[min((unsigned)(b - T.cs_lo), (unsigned)T.cs_n)];
+__device__ __forceinline__ size_t table_floats2(const GeomDev &g) {
+    return (size_t)(g.n_r + 1) + (g.n_h + 1) + (g.n_theta + 1);
 }
 
-__device__ __forceinline__ size_t table_floats2(const GeomDev &g, bool all = true) {
-    return (all ? (size_t)(g.n_r + 1) + (g.n_h + 1) : 0) + (g.n_theta + 1);
-}
-
-// Cooperative copy of the grid tables into LDS; the caller synchronises.
-// all = false stages only the sector edges (the one table the traversal loop
-// reads) and leaves the radii and planes in global memory.
-__device__ __forceinline__ Tabs stage_tables(const GeomDev &g, float2 *smem, bool all = true) {
-    const int nr = all ? g.n_r + 1 : 0, nh = all ? g.n_h + 1 : 0, nc = g.n_theta + 1;
+// Cooperative copy of the grid tables (radii, planes, sector edges in the
+// object frame) into LDS; the caller synchronises.
+__device__ __forceinline__ Tabs stage_tables(const GeomDev &g, float2 *smem) {
+    const int nr = g.n_r + 1, nh = g.n_h + 1, nc = g.n_theta + 1;
     for (int i = threadIdx.x; i < nr; i += blockDim.x) smem[i] = g.r_tab[i];
     for (int i = threadIdx.x; i < nh; i += blockDim.x) smem[nr + i] = g.h_tab[i];
     for (int i = threadIdx.x; i < nc; i += blockDim.x) smem[nr + nh + i] = g.cs_tab[i];
     Tabs T;
-    T.r = all ? smem : g.r_tab;
-    T.h = all ? smem + nr : g.h_tab;
+    T.r = smem;
+    T.h = smem + nr;
     T.cs = smem + nr + nh;
     T.cs_lo = 0;
     T.cs_n = g.n_theta;
     return T;
 }
 
-// Sector edges lo .. hi only (a super-block's wedge), staged in LDS, with the
-// radii and planes left in global memory; the caller synchronises.
-__device__ __forceinline__ Tabs stage_edges(const GeomDev &g, float2 *smem, int lo, int hi) {
-    for (int i = threadIdx.x; i <= hi - lo; i += blockDim.x) smem[i] = g.cs_tab[lo + i];
-    Tabs T;
-    T.r = g.r_tab;
-    T.h = g.h_tab;
-    T.cs = smem;
-    T.cs_lo = lo;
-    T.cs_n = hi - lo;
-    return T;
-}
-
-// ------------------------------------------------------------ per-ray set-up
-
-enum : int { RAY_HIT = 1, RAY_AXIAL = 2, RAY_THRU = 4 };
-
-struct RayF {
-    float cx, cy;      // closest point to the axis (xy), s = 0
-    float ex, ey, ez;  // unit direction
-    float zc, zclo;    // z at s = 0 as hi + lo (shallow rays amplify its rounding)
-    float inv_ez;      // 1 / e_z
-    float b, blo;      // closest-approach distance as hi + lo
-    float inv_k;       // |d| / |d_xy|
-    float s_in, s_out; // parameter interval inside the grid support
-    int flags;
-    int it_in, it_out; // sectors before / after the axis for rays through it
-    float len;         // |d|
-    int pix;           // u | v << 16 (the rare FP64 path rebuilds the ray from it)
-};
-
-// Sector containing the direction (x, y).
-__device__ __forceinline__ int sector_of(const GeomDev &g, float x, float y) {
-    if (g.n_theta == 1) return 0;
-    const float two_pi = 6.28318530717958647692f;
-    float th = atan2f(y, x) - g.theta0;
-    th -= two_pi * floorf(th * (1.0f / two_pi));
-    int it = (int)floorf(th * g.inv_dtheta);
-    it = it < 0 ? 0 : it;
-    return it >= g.n_theta ? g.n_theta - 1 : it;
-}
-
-// Parameter where the ray meets shell radius rt (hi, lo): the magnitude
-// sqrt((r - b)(r + b)) / kappa, or -1 if the ray passes outside the shell.
-__device__ __forceinline__ float shell_w(float2 rt, const RayF &r) {
-    float diff = (rt.x - r.b) + (rt.y - r.blo);
-    if (!(diff > 0.0f)) return -1.0f;
-    return fsqrt(diff * (rt.x + r.b)) * r.inv_k;
-}
-
-// Parameter where the ray meets the axial plane ht (hi, lo).
-__device__ __forceinline__ float plane_s(float2 ht, const RayF &r) {
-    return ((ht.x - r.zc) + (ht.y - r.zclo)) * r.inv_ez;
-}
-
-// Crossing of the ray with the full line through the axis along sector edge
-// b.  s: the parameter; ne, nc: n.e_xy and n.c with n = (-sin, cos) of the
-// edge (their signs give the side of the line, for half-plane tests);
-// on_edge: the meeting is on the edge's half-line (the ray sweeps less than
-// pi, so the edge direction must lie within 90 degrees of the closest point c).
-// When the ray runs nearly parallel to the edge line (|n.e| < kEdgeTau, only
-// rays passing close to the axis), the FP32 quotient is ill-conditioned and the
-// crossing is solved in FP64 on the unrounded ray.
-// 1/32: the FP32 quotient's error stays below ~1e-4 mm at the threshold, and
-// whole waves take the FP64 branch when one lane needs it (at 1/16 the branch
-// cost ~9% of the back-projection).
-constexpr float kEdgeTau = 0.03125f;
-
-struct EdgeX {
-    float s, ne, nc;
-    bool on_edge;
-};
-
-// FP64 re-solve of a sector-edge crossing for a ray nearly parallel to the
-// edge line (rare: rays within a few mm of the axis).
-__device__ __forceinline__ void edge_cross_fp64(double2 c, const ViewDev *V, int pix, float len, EdgeX *x) {
-    const double fu = (double)(pix & 0xffff), fv = (double)(pix >> 16);
-    const double dxd = fma(fv, V->V[0], fma(fu, V->U[0], V->d0[0]));
-    const double dyd = fma(fv, V->V[1], fma(fu, V->U[1], V->d0[1]));
-    const double A = fma(dxd, dxd, dyd * dyd);
-    const double tcd = A > 0.0 ? -fma(V->a[0], dxd, V->a[1] * dyd) / A : 0.0;
-    const double nd = c.x * dyd - c.y * dxd;
-    const double na = c.x * V->a[1] - c.y * V->a[0];
-    x->ne = (float)nd;
-    x->nc = (float)na;
-    if (nd == 0.0) {
-        x->on_edge = false;
-        x->s = CYL_INF;
-        return;
-    }
-    const double t = -na / nd;
-    const double px = fma(t, dxd, V->a[0]), py = fma(t, dyd, V->a[1]);
-    x->on_edge = (c.x * px + c.y * py) > 0.0;
-    x->s = (float)((t - tcd) * (double)len);
-}
-
-// cs: (cos, sin) of edge b (from the table).  refine = false skips the FP64
-// re-solve (for candidates that are computed but not used).
-__device__ __forceinline__ EdgeX edge_cross(const GeomDev &g, const ViewDev &V, const RayF &r, float2 cs, int b,
-                                            bool refine = true) {
-    EdgeX x;
-    x.nc = cs.x * r.cy - cs.y * r.cx;
-    x.ne = cs.x * r.ey - cs.y * r.ex;
-    x.on_edge = (cs.x * r.cx + cs.y * r.cy) > 0.0f;
-    x.s = -x.nc * frcp(x.ne);
-    if (refine && fabsf(x.ne) < kEdgeTau && !(r.flags & RAY_AXIAL)) edge_cross_fp64(g.cs64[b], &V, r.pix, r.len, &x);
-    return x;
-}
-
-// Mostly-FP32 ray set-up shared by every kernel.  FP64 is used for the pixel
-// direction, the closest-approach parameter (one FP64 Newton step on an FP32
-// quotient), the closest point and its distance.
-// SUPPORT = false skips the grid-support interval (callers that clip to a
-// smaller region themselves): the interval is then the source-pixel segment.
-template <bool SUPPORT = true>
-__device__ __forceinline__ void ray_geom(const GeomDev &g, const Tabs &T, const ViewDev &V, int u, int v,
-                                         RayF &r, double &dxo, double &dyo, double &dzo, double &tco) {
-    const double fu = (double)u, fv = (double)v;
-    const double dx = fma(fv, V.V[0], fma(fu, V.U[0], V.d0[0]));
-    const double dy = fma(fv, V.V[1], fma(fu, V.U[1], V.d0[1]));
-    const double dz = fma(fv, V.V[2], fma(fu, V.U[2], V.d0[2]));
-    dxo = dx;
-    dyo = dy;
-    dzo = dz;
-    const double A = fma(dx, dx, dy * dy);
-    const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
-    const float len = fsqrt(fmaf(fdx, fdx, fmaf(fdy, fdy, fdz * fdz)));
-    const float il = frcp(len);
-    r.ex = fdx * il;
-    r.ey = fdy * il;
-    r.ez = fdz * il;
-    r.flags = 0;
-    r.len = len;
-    r.pix = u | (v << 16);
-    r.it_in = r.it_out = 0;
-    double tc;
-    if (A > 0.0) {
-        const double B = fma(V.a[0], dx, V.a[1] * dy);
-        const float Af = (float)A;
-        const float rA = frcp(Af);
-        const float t0 = -(float)B * rA;
-        const double res = fma(-(double)t0, A, -B);  // -B - t0 A
-        tc = (double)t0 + (double)((float)res * rA);
-        r.inv_k = len * __builtin_amdgcn_rsqf(Af);
-    } else {
-        // parallel to the axis: put s = 0 at mid-height of the grid
-        r.flags |= RAY_AXIAL;
-        tc = (dz != 0.0) ? (0.5 * (g.h_min_d + g.h_max_d) - V.a[2]) / dz : 0.0;
-        tc = tc < 0.0 ? 0.0 : (tc > 1.0 ? 1.0 : tc);
-        r.inv_k = CYL_INF;
-    }
-    tco = tc;
-    const double cxd = fma(tc, dx, V.a[0]);
-    const double cyd = fma(tc, dy, V.a[1]);
-    const double b2 = fma(cxd, cxd, cyd * cyd);
-    const float bf = fsqrt((float)b2);
-    r.b = bf;
-    r.blo = bf > 0.0f ? (float)fma(-(double)bf, (double)bf, b2) * (0.5f * frcp(bf)) : 0.0f;
-    r.cx = (float)cxd;
-    r.cy = (float)cyd;
-    const double zcd = fma(tc, dz, V.a[2]);
-    r.zc = (float)zcd;
-    r.zclo = (float)(zcd - (double)r.zc);
-    r.inv_ez = (fdz != 0.0f) ? len / fdz : CYL_INF;
-    float s0 = -(float)tc * len, s1 = (float)(1.0 - tc) * len;
-    // support interval with the same crossing formulas as the traversal
-    bool hit = true;
-    if (!(r.flags & RAY_AXIAL)) {
-        if (SUPPORT) {
-            const float w = shell_w(T.r[g.n_r], r);
-            if (w < 0.0f) hit = false;
-            s0 = fmaxf(s0, -w);
-            s1 = fminf(s1, w);
-        }
-        if (bf == 0.0f && g.n_theta > 1) {
-            r.flags |= RAY_THRU;
-            r.it_in = sector_of(g, -r.ex, -r.ey);
-            r.it_out = sector_of(g, r.ex, r.ey);
-        }
-    } else if (SUPPORT) {
-        const float2 rt = T.r[g.n_r];
-        if (!((rt.x - r.b) + (rt.y - r.blo) > 0.0f)) hit = false;
-    }
-    if (!SUPPORT) {
-    } else if (fdz != 0.0f) {
-        const float t1 = plane_s(T.h[0], r), t2 = plane_s(T.h[g.n_h], r);
-        s0 = fmaxf(s0, fminf(t1, t2));
-        s1 = fminf(s1, fmaxf(t1, t2));
-    } else if (!(r.zc >= T.h[0].x && r.zc < T.h[g.n_h].x)) {
-        hit = false;
-    }
-    r.s_in = s0;
-    r.s_out = s1;
-    if (hit && s1 > s0) r.flags |= RAY_HIT;
-}
-
-// Closed-form row sum L_j in FP64: length inside the support minus the hole.
-__device__ __forceinline__ float row_sum_fp64(const GeomDev &g, const ViewDev &V, const RayF &r, double dx,
-                                              double dy, double dz, double tc) {
-    if (!(r.flags & RAY_HIT)) return 0.0f;
-    const double A = fma(dx, dx, dy * dy);
-    const double len = sqrt(A + dz * dz);
-    double lo = -tc * len, hi = (1.0 - tc) * len;
-    const double cxd = fma(tc, dx, V.a[0]), cyd = fma(tc, dy, V.a[1]);
-    const double b = sqrt(fma(cxd, cxd, cyd * cyd));
-    double ik = 0.0;
-    if (A > 0.0) {
-        ik = len / sqrt(A);
-        if (!(b < g.r_max_d)) return 0.0f;
-        const double w = sqrt((g.r_max_d - b) * (g.r_max_d + b)) * ik;
-        lo = fmax(lo, -w);
-        hi = fmin(hi, w);
-    } else if (!(b < g.r_max_d)) {
-        return 0.0f;
-    }
-    if (dz != 0.0) {
-        const double zc = fma(tc, dz, V.a[2]);
-        const double t1 = (g.h_min_d - zc) * len / dz, t2 = (g.h_max_d - zc) * len / dz;
-        lo = fmax(lo, fmin(t1, t2));
-        hi = fmin(hi, fmax(t1, t2));
-    }
-    if (!(hi > lo)) return 0.0f;
-    double L = hi - lo;
-    if (g.r_min_d > 0.0 && b < g.r_min_d) {
-        if (A > 0.0) {
-            const double w = sqrt((g.r_min_d - b) * (g.r_min_d + b)) * ik;
-            L -= fmax(0.0, fmin(hi, w) - fmax(lo, -w));
-        } else {
-            L = 0.0;
-        }
-    }
-    return (float)fmax(L, 0.0);
-}
-
-// Cell at parameter s (indices clamped into the grid; ir = -1 inside the hole).
-__device__ __forceinline__ void cell_at(const GeomDev &g, const RayF &r, float s, int &ih, int &it, int &ir) {
-    const float x = fmaf(s, r.ex, r.cx), y = fmaf(s, r.ey, r.cy), z = fmaf(s, r.ez, r.zc);
-    const float q = s / r.inv_k;
-    const float rr = fsqrt(fmaf(r.b, r.b, q * q));
-    const int h = (int)floorf((z - g.h_min) * g.inv_dh);
-    ih = h < 0 ? 0 : (h >= g.n_h ? g.n_h - 1 : h);
-    const int ri = (int)floorf((rr - g.r_min) * g.inv_dr);
-    ir = ri < -1 ? -1 : (ri >= g.n_r ? g.n_r - 1 : ri);
-    if (r.flags & RAY_THRU)
-        it = (s < 0.0f) ? r.it_in : r.it_out;
-    else
-        it = sector_of(g, x, y);
-}
-
-// ------------------------------------------------------------ traversal
-
-__device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
-
-// Shell and plane offsets of a ray, rebased at the shell nearest to b and the
-// plane nearest to z_c:  r_i - b = (i - ic) dr + (r_ic - b) and
-// h_m - z_c = (m - mc) dh + (h_mc - z_c), with dr, dh as two FP32 words, so
-// the crossings need no table read and keep the precision of r - b at
-// grazing incidence and of h - z_c for shallow rays.
-struct Rebase {
-    int ic, mc;
-    float drc, dzc;
-};
-
-__device__ __forceinline__ Rebase rebase(const GeomDev &g, const Tabs &T, const RayF &r) {
-    Rebase q;
-    q.ic = clampi((int)floorf((r.b - g.r_min) * g.inv_dr + 0.5f), 0, g.n_r);
-    const float2 rt = T.r[q.ic];
-    q.drc = (rt.x - r.b) + (rt.y - r.blo);
-    q.mc = clampi((int)floorf((r.zc - g.h_min) * g.inv_dh + 0.5f), 0, g.n_h);
-    const float2 ht = T.h[q.mc];
-    q.dzc = (ht.x - r.zc) + (ht.y - r.zclo);
-    return q;
-}
-
-// Index box of a walk: it ends as soon as an index leaves [lo, lo + n).
-struct Box {
-    int hlo, hn, tlo, tn, rlo, rn;
-};
-
-// Per-ray constants of the walk.
-//  planes: s_m = k zA + (k zAlo + zB), k = m - mc, i.e. (h_m - z_c) / e_z with
-//    the products by 1/e_z taken once per ray (zB = +inf for level rays);
-//  shells: d_i = r_i - b = k dr + (k dr_lo + drc), k = i - ic (drc = +inf for
-//    rays parallel to the axis, which cross no shell); ib is the innermost
-//    shell the ray reaches (r_ib > b), so the next shell before the closest
-//    approach is r_ir if ir >= ib, else the ray turns and leaves through
-//    r_{ir+1};
-//  sector edges: with (cx, cy, ex, ey) multiplied by the sweep direction, the
-//    edge's half-line is met ahead iff n.e > 0 (e_xy is perpendicular to c, so
-//    n.e = +-|e_xy| (m.c)/b with m the edge direction), at s = -(n.c)/(n.e).
-struct Walk {
-    float zA, zAlo, zB;
-    int kz, dir_h;
-    float drc, twob;
-    int ic, ib;
-    float tcx, tcy, tex, tey;
-    int dir_t, up_t, tstep, twrap;
-};
-
-__device__ __forceinline__ Walk walk_setup(const GeomDev &g, const Tabs &T, const RayF &r, int it) {
-    const Rebase q = rebase(g, T, r);
-    Walk w;
-    w.dir_h = r.ez > 0.0f ? 1 : (r.ez < 0.0f ? -1 : 0);
-    if (w.dir_h != 0) {
-        w.zA = g.dh * r.inv_ez;
-        w.zAlo = g.dh_lo * r.inv_ez;
-        w.zB = q.dzc * r.inv_ez;
-    } else {
-        w.zA = w.zAlo = 0.0f;
-        w.zB = CYL_INF;
-    }
-    w.kz = (w.dir_h > 0 ? 1 : 0) - q.mc;
-    w.ic = q.ic;
-    w.ib = (r.flags & RAY_AXIAL) ? 0x7fffffff : q.ic + (q.drc > 0.0f ? 0 : 1);
-    w.drc = (r.flags & RAY_AXIAL) ? CYL_INF : q.drc;
-    w.twob = 2.0f * r.b;
-    const float cross = r.cx * r.ey - r.cy * r.ex;
-    const int nt = g.n_theta;
-    w.dir_t = (nt == 1 || (r.flags & (RAY_AXIAL | RAY_THRU))) ? 0 : (cross > 0.0f ? 1 : (cross < 0.0f ? -1 : 0));
-    w.up_t = w.dir_t > 0 ? 1 : 0;
-    // a ray through the axis jumps from the start sector to the one ahead
-    w.tstep = (r.flags & RAY_THRU) ? r.it_out - it : w.dir_t;
-    w.twrap = w.dir_t * nt;
-    const float sg = w.dir_t < 0 ? -1.0f : 1.0f;
-    w.tcx = sg * r.cx;
-    w.tcy = sg * r.cy;
-    w.tex = sg * r.ex;
-    w.tey = sg * r.ey;
-    return w;
-}
-
-// Next shell crossing after s from ring ir (not clamped to s).
-__device__ __forceinline__ float shell_next(const GeomDev &g, const Walk &w, const RayF &r, int ir, float s,
-                                            int &r_dir) {
-    const bool inward = (s < 0.0f) && (ir >= w.ib);
-    const float k = (float)((inward ? ir : ir + 1) - w.ic);
-    const float d = fmaxf(fmaf(k, g.dr, fmaf(k, g.dr_lo, w.drc)), 0.0f);
-    const float x = fsqrt(d * (d + w.twob)) * r.inv_k;
-    r_dir = inward ? -1 : 1;
-    return inward ? -x : x;
-}
-
-// Crossing of plane m = ih + (dir_h > 0).
-__device__ __forceinline__ float plane_next(const Walk &w, int ih) {
-    const float k = (float)(ih + w.kz);
-    return fmaf(k, w.zA, fmaf(k, w.zAlo, w.zB));
-}
-
-// Crossing of sector edge be (cs = its cos, sin) ahead of s, or +inf.  An
-// edge-half-line meeting behind s means the start cell was one sector short
-// (rounding at entry): cross it at once.  Near-parallel cases (|n.e| below
-// kEdgeTau) are re-solved in FP64 when `refine` is set.
-__device__ __forceinline__ float edge_next(const ViewDev &V, const GeomDev &g, const Walk &w, const RayF &r,
-                                           float2 cs, int be, float s, bool refine) {
-    const float nc = cs.x * w.tcy - cs.y * w.tcx;
-    const float ne = cs.x * w.tey - cs.y * w.tex;
-    float x = -nc * frcp(ne);
-    bool ahead = ne > 0.0f;
-    if (refine && w.dir_t != 0 && fabsf(ne) < kEdgeTau) {
-        EdgeX e;
-        edge_cross_fp64(g.cs64[be], &V, r.pix, r.len, &e);
-        x = e.s;
-        ahead = e.on_edge;
-    }
-    return (w.dir_t != 0 && ahead) ? vmax(x, s) : CYL_INF;
-}
-
-// Walk the ray from s to s_end starting in cell (ih, it, ir) and call
-// visit(ih, it, ir, length) for every piece (length 0 allowed; ir = -1 is the
-// hole), and visit.late() at the end of each step (and once after the walk)
-// for work the visitor wants to spread out.  The walk also ends when an index
-// leaves the box bx.  Each step takes the nearest of the three next-crossing
-// candidates and recomputes the candidate of that kind with selects (no
-// divergent branch but the rare FP64 edge case); shell and plane crossings are
-// arithmetic, so the only table read per step is the next sector edge, issued
-// before the visitor so that its latency overlaps the visitor's work.  Plane
-// and shell candidates after their own event are monotone in the index, so
-// only the first ones and the edge candidates are clamped to s.
-template <bool CHECK_T, bool PART, class Visit>
-__device__ __forceinline__ void traverse(const GeomDev &g, const Tabs &T, const ViewDev &V, const RayF &r, float s,
-                                         const float s_end, int ih, int it, int ir, const Box &bx, Visit &visit) {
-    const int nt = g.n_theta;
-    const Walk w = walk_setup(g, T, r, it);
-    int r_dir;
-    float s_z = fmaxf(plane_next(w, ih), s);
-    float s_r = fmaxf(shell_next(g, w, r, ir, s, r_dir), s);
-    float s_t;
-    if (r.flags & RAY_THRU)
-        s_t = s < 0.0f ? 0.0f : CYL_INF;
-    else
-        s_t = edge_next(V, g, w, r, PART ? edge_at(T, it + w.up_t) : T.cs[it + w.up_t], it + w.up_t, s, true);
-    const int max_steps = 2 * g.n_r + nt + g.n_h + 8;
-    for (int n = 0; n < max_steps; ++n) {
-        const float sn = vmin(vmin3(s_z, s_r, s_t), s_end);
-        const bool ev_z = (sn == s_z);
-        const bool ev_r = !ev_z && (sn == s_r);
-        const bool ev_t = !ev_z && !ev_r;
-        int itn = it + (ev_t ? w.tstep : 0);
-        itn -= ((unsigned)itn >= (unsigned)nt) ? w.twrap : 0;
-        const int be = itn + w.up_t;
-        const float2 cse = PART ? edge_at(T, be) : T.cs[be];
-        visit(ih, it, ir, sn - s);
-        s = sn;
-        ih += ev_z ? w.dir_h : 0;
-        ir += ev_r ? r_dir : 0;
-        it = itn;
-        if (!(sn < s_end) || (unsigned)(ih - bx.hlo) >= (unsigned)bx.hn ||
-            (unsigned)(ir - bx.rlo) >= (unsigned)bx.rn || (CHECK_T && (unsigned)(it - bx.tlo) >= (unsigned)bx.tn))
-            break;
-        int rd;
-        const float nz = plane_next(w, ih);
-        const float nrr = shell_next(g, w, r, ir, s, rd);
-        const float ntt = edge_next(V, g, w, r, cse, be, s, ev_t);
-        s_z = ev_z ? nz : s_z;
-        s_r = ev_r ? nrr : s_r;
-        r_dir = ev_r ? rd : r_dir;
-        s_t = ev_t ? ntt : s_t;
-        visit.late();
-    }
-    visit.late();
+// Frame of a whole-ray walk: the object frame, with the reference point
+// nearest the grid centre.
+__device__ __forceinline__ Frame grid_frame(const GeomDev &g) {
+    Frame F;
+    F.cw = 1.0;
+    F.sw = 0.0;
+    F.gx = F.gy = 0.0f;
+    F.gz = (float)(0.5 * (g.h_min_d + g.h_max_d));
+    F.wsec = -g.theta0 * g.inv_dtheta;
+    return F;
 }
 
 // Minimum and maximum over the 64 lanes of a wave (all lanes active).
@@ -646,36 +126,36 @@ static_assert(sizeof(FpLaunch) <= 4096 && sizeof(BpLaunch) <= 4096, "kernel argu
 // Partial forward projection of piece `piece` of `npieces` equal parameter
 // ranges of ray (u, v): each piece starts from its own cell so the pieces of
 // one ray can run on neighbouring lanes.
-template <int VT>
-__device__ __forceinline__ float fp_piece(const GeomDev &g, const Tabs &T, const ViewDev &V, const RayF &r,
-                                          __amdgpu_buffer_rsrc_t vol, int piece, int npieces) {
+template <int VT, bool PRECISE>
+__device__ __forceinline__ float fp_piece(const GeomDev &g, const Tabs &T, const ViewDev &V, const Frame &F,
+                                          const Ray &r, __amdgpu_buffer_rsrc_t vol, int piece, int npieces) {
     if (!(r.flags & RAY_HIT)) return 0.0f;
     const float span = (r.s_out - r.s_in) / (float)npieces;
     const float a0 = piece == 0 ? r.s_in : fmaf((float)piece, span, r.s_in);
     const float a1 = piece == npieces - 1 ? r.s_out : fmaf((float)(piece + 1), span, r.s_in);
     if (!(a1 > a0)) return 0.0f;
     int ih, it, ir;
-    cell_at(g, r, a0, ih, it, ir);
+    cell_at(g, r, F, a0, ih, it, ir);
     // the gather of one step is consumed at the start of the next (before the
     // next gather is issued, so the two share a register and the wait for the
     // load falls a whole step later); cell indices fit in 24-bit products
     // (checked when the geometry is created)
     struct Gather {
         __amdgpu_buffer_rsrc_t vol;
-        int nt, nr, ntr;
+        int nh, nt, nr, ntr;
         float acc, plen, pval;
         __device__ __forceinline__ void operator()(int h, int t, int q, float len) {
-            const unsigned idx = __umul24(h, ntr) + __umul24(t, nr) + (q < 0 ? 0 : q);
+            // a slab index outside the grid (a step of rounding past its end
+            // faces) addresses past the volume, where the buffer load reads 0
+            const unsigned idx = __umul24(min((unsigned)h, (unsigned)nh), ntr) + __umul24(t, nr) + (q < 0 ? 0 : q);
             // kept in place (volatile) so the compiler neither sinks it to the end
             // of the step nor copies the loaded value
             asm volatile("v_fmac_f32 %0, %1, %2" : "+v"(acc) : "v"(plen), "v"(pval));
             pval = Store<VT>::ldb(vol, idx);
             plen = q < 0 ? 0.0f : len;
         }
-        __device__ __forceinline__ void late() {}
-    } visit{vol, g.n_theta, g.n_r, g.n_theta * g.n_r, 0.0f, 0.0f, 0.0f};
-    const Box bx{0, g.n_h, 0, g.n_theta, -1, g.n_r + 1};
-    traverse<false, false>(g, T, V, r, a0, a1, ih, it, ir, bx, visit);
+    } visit{vol, g.n_h, g.n_theta, g.n_r, g.n_theta * g.n_r, 0.0f, 0.0f, 0.0f};
+    traverse<true, false, PRECISE>(g, T, V, r, a0, a1, ih, it, ir, visit);
     return fmaf(visit.plen, visit.pval, visit.acc);
 }
 
@@ -712,13 +192,19 @@ __global__ __launch_bounds__(256) void fp_kernel(const FpLaunch L) {
     const int v = (tile / tiles_u) * 8 + (lane >> 3);
     const bool live = u < g.cols && v < g.rows;
     const ViewDev &V = g.views[k];
-    RayF r;
-    double dx, dy, dz, tc;
-    ray_geom(g, T, V, live ? u : 0, live ? v : 0, r, dx, dy, dz, tc);
-    if (!live) r.flags = 0;
+    const Frame F = grid_frame(g);
+    Ray r;
+    double dx, dy, dz;
+    ray_setup(g, V, live ? u : 0, live ? v : 0, F, r, dx, dy, dz);
+    if (live && clip_support(g, T, r)) r.flags |= RAY_HIT;
     const __amdgpu_buffer_rsrc_t vrs =
         buffer_rsrc(vol, (unsigned)g.n_h * (unsigned)g.n_theta * (unsigned)g.n_r * (unsigned)Store<VT>::kSize);
-    float acc = fp_piece<VT>(g, T, V, r, vrs, piece, nsplit);
+    // rays whose reference point lies far from their closest approach (nearly
+    // parallel to the axis) need the shell roots as small differences; a
+    // wave-wide choice
+    const bool far_ref = (r.flags & RAY_HIT) && (r.k2 < 0.25f || fabsf(r.sc) > (float)g.r_max_d);
+    float acc = __ballot(far_ref) ? fp_piece<VT, true>(g, T, V, F, r, vrs, piece, nsplit)
+                                  : fp_piece<VT, false>(g, T, V, F, r, vrs, piece, nsplit);
     if (nsplit > 1) {
         part[threadIdx.x] = acc;
         __syncthreads();
@@ -733,7 +219,7 @@ __global__ __launch_bounds__(256) void fp_kernel(const FpLaunch L) {
     }
     float rj = 0.0f;
     if (live) {
-        const float L = row_sum_fp64(g, V, r, dx, dy, dz, tc);
+        const float L = (r.flags & RAY_HIT) ? row_sum_fp64(g, V, dx, dy, dz) : 0.0f;
         const float pj = Store<PT>::ld(proj, j);
         const float w = pw ? ld_any(pw, pwt, j) : 1.0f;
         rj = (L > 0.0f) ? w * (pj - acc) / L : 0.0f;
@@ -762,32 +248,34 @@ __global__ __launch_bounds__(256) void record_kernel(GeomDev g, int view, int fi
     if (pix >= g.rows * g.cols) return;
     const int u = pix % g.cols, v = pix / g.cols;
     const ViewDev &V = g.views[view];
-    RayF r;
-    double dx, dy, dz, tc;
-    ray_geom(g, T, V, u, v, r, dx, dy, dz, tc);
+    const Frame F = grid_frame(g);
+    Ray r;
+    double dx, dy, dz;
+    ray_setup(g, V, u, v, F, r, dx, dy, dz);
+    if (clip_support(g, T, r)) r.flags |= RAY_HIT;
     struct Record {
         int32_t *cells;
         float *lens;
-        int nt, nr, n, pos, cap;
+        int nh, nt, nr, n, pos, cap;
         __device__ __forceinline__ void operator()(int h, int t, int q, float len) {
-            if (q < 0 || !(len > 0.0f)) return;
+            // the walk may leave the grid by a step of rounding at its faces:
+            // record only cells of the grid
+            if (q < 0 || q >= nr || (unsigned)h >= (unsigned)nh || !(len > 0.0f)) return;
             if (n < cap) {
                 cells[pos + n] = (h * nt + t) * nr + q;
                 lens[pos + n] = len;
             }
             ++n;
         }
-        __device__ __forceinline__ void late() {}
-    } rec{cells, lens, g.n_theta, g.n_r, 0, fill ? rowptr[pix] : 0, fill ? rowptr[pix + 1] - rowptr[pix] : 0};
+    } rec{cells, lens, g.n_h, g.n_theta, g.n_r, 0, fill ? rowptr[pix] : 0, fill ? rowptr[pix + 1] - rowptr[pix] : 0};
     if ((r.flags & RAY_HIT) && r.s_out > r.s_in) {
         int ih, it, ir;
-        cell_at(g, r, r.s_in, ih, it, ir);
-        const Box bx{0, g.n_h, 0, g.n_theta, -1, g.n_r + 1};
-        traverse<false, false>(g, T, V, r, r.s_in, r.s_out, ih, it, ir, bx, rec);
+        cell_at(g, r, F, r.s_in, ih, it, ir);
+        traverse<true, false, true>(g, T, V, r, r.s_in, r.s_out, ih, it, ir, rec);
     }
     if (!fill) {
         counts[pix] = rec.n;
-        rowsum[pix] = row_sum_fp64(g, V, r, dx, dy, dz, tc);
+        rowsum[pix] = (r.flags & RAY_HIT) ? row_sum_fp64(g, V, dx, dy, dz) : 0.0f;
     } else {
         // a row the fill pass found shorter is padded with empty entries
         for (int i = rec.n; i < rec.cap; ++i) {
@@ -798,26 +286,20 @@ __global__ __launch_bounds__(256) void record_kernel(GeomDev g, int view, int fi
 }
 
 __global__ __launch_bounds__(256) void rowsum_kernel(GeomDev g, float *__restrict__ out, int view_begin) {
-    extern __shared__ float2 smem[];
-    const Tabs T = stage_tables(g, smem);
-    __syncthreads();
     const int k = view_begin + blockIdx.y;
     const int tiles_u = (g.cols + 15) / 16;
     const int u = (blockIdx.x % tiles_u) * 16 + (threadIdx.x & 15);
     const int v = (blockIdx.x / tiles_u) * 16 + (threadIdx.x >> 4);
     if (u >= g.cols || v >= g.rows) return;
     const ViewDev &V = g.views[k];
-    RayF r;
-    double dx, dy, dz, tc;
-    ray_geom(g, T, V, u, v, r, dx, dy, dz, tc);
-    out[((size_t)k * g.rows + v) * g.cols + u] = row_sum_fp64(g, V, r, dx, dy, dz, tc);
+    const double fu = (double)u, fv = (double)v;
+    const double dx = fma(fv, V.V[0], fma(fu, V.U[0], V.d0[0]));
+    const double dy = fma(fv, V.V[1], fma(fu, V.U[1], V.d0[1]));
+    const double dz = fma(fv, V.V[2], fma(fu, V.U[2], V.d0[2]));
+    out[((size_t)k * g.rows + v) * g.cols + u] = row_sum_fp64(g, V, dx, dy, dz);
 }
 
 // ------------------------------------------------------------ back-projection
-
-struct Block {
-    int hA, hB, tA, tB, rA, rB;
-};
 
 // Projection of one bounding point of the block's convex hull
 // slab x wedge x disc(r_B) in view V, for point index `pt` (two z levels per
@@ -935,60 +417,20 @@ __device__ bool footprint(const GeomDev &g, const Tabs &T, const ViewDev &V, con
     return any;
 }
 
-// Parameter interval of the ray inside the block hull (slab x wedge x disc),
-// from the same crossing formulas as the traversal.
-template <bool PART>
-__device__ __forceinline__ bool clip_block(const GeomDev &g, const Tabs &T, const ViewDev &V, const RayF &r,
-                                           const Block &B, float &s0, float &s1) {
-    s0 = r.s_in;
-    s1 = r.s_out;
-    if (r.ez != 0.0f) {
-        const float t1 = plane_s(T.h[B.hA], r), t2 = plane_s(T.h[B.hB], r);
-        s0 = fmaxf(s0, fminf(t1, t2));
-        s1 = fminf(s1, fmaxf(t1, t2));
-    } else if (!(r.zc >= T.h[B.hA].x && r.zc < T.h[B.hB].x)) {
-        return false;
-    }
-    if (!(r.flags & RAY_AXIAL)) {
-        const float w = shell_w(T.r[B.rB], r);
-        if (w < 0.0f) return false;
-        s0 = fmaxf(s0, -w);
-        s1 = fminf(s1, w);
-    } else {
-        const float2 rt = T.r[B.rB];
-        if (!((rt.x - r.b) + (rt.y - r.blo) > 0.0f)) return false;
-    }
-    if (B.tB - B.tA < g.n_theta) {
-        // lower edge: n_A . p >= 0 ; upper edge: n_B . p <= 0
-        for (int e = 0; e < 2; ++e) {
-            const int eb = e == 0 ? B.tA : B.tB;
-            const EdgeX x = edge_cross(g, V, r, PART ? edge_at(T, eb) : T.cs[eb], eb);
-            const float sg = e == 0 ? 1.0f : -1.0f;
-            if (x.ne == 0.0f) {
-                // parallel to the edge line: a ray on the line belongs to the
-                // sector on the + side, i.e. to the block whose lower edge it is
-                if (e == 0 ? (x.nc < 0.0f) : (x.nc >= 0.0f)) return false;
-                continue;
-            }
-            if (sg * x.ne > 0.0f)
-                s0 = fmaxf(s0, x.s);
-            else
-                s1 = fminf(s1, x.s);
-        }
-    }
-    return s1 > s0;
-}
-
-// Accumulator slot of block-local cell (h, t, q): rows of br + 1 and planes of
-// bt (br + 1) + 1 words, odd strides so neighbouring cells in theta and h fall
-// in different LDS banks.
+// Accumulator slot of block-local cell (h, t, q): rows of wr + 1 words (the
+// last a spare), planes of wt + 2 rows (the first and last spare) plus one
+// word, odd strides so neighbouring cells in theta and h fall in different LDS
+// banks.  A walk that steps one cell past the block's theta faces or its
+// radial faces (rounding at a face) lands in a spare word; one past its h
+// faces lands below 0 or at or above block_slots - 1, where the scatter
+// clamps it to the last word, a spare too.
+__device__ __forceinline__ int slot_rs(const Block &B) { return (B.rB - B.rA) + 1; }
+__device__ __forceinline__ int slot_ps(const Block &B) { return (B.tB - B.tA + 2) * slot_rs(B) + 1; }
 __device__ __forceinline__ int slot(const Block &B, int h, int t, int q) {
-    const int rs = (B.rB - B.rA) + 1;
-    const int ps = (B.tB - B.tA) * rs + 1;
-    return h * ps + t * rs + q;
+    return h * slot_ps(B) + (t + 1) * slot_rs(B) + q;
 }
 
-__device__ __forceinline__ int block_slots(const Block &B) { return slot(B, B.hB - B.hA, 0, 0) + 1; }
+__device__ __forceinline__ int block_slots(const Block &B) { return (B.hB - B.hA) * slot_ps(B) + 1; }
 
 // Trace ray (u, v) of view V through block B (a block or a super-block) and
 // add its lengths into one 64-bit fixed-point accumulator per cell,
@@ -997,110 +439,25 @@ __device__ __forceinline__ int block_slots(const Block &B) { return slot(B, B.hB
 // do not depend on their order.  The scales keep |c| and n below 2^31 (see
 // sart_scales), so the low word never carries into the high word; yj is
 // y_j cscale, and nscale = 0 accumulates c alone.
-template <bool PART>
-__device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const ViewDev &V, const Block &B, int u,
-                                       int v, float yj, unsigned long long *acc64, float nscale) {
-    RayF r;
-    double dx, dy, dz, tc;
-    ray_geom<false>(g, T, V, u, v, r, dx, dy, dz, tc);  // the block clip bounds the walk
-    if (!(r.flags & RAY_HIT)) return;
-    float s0, s1;
-    if (!clip_block<PART>(g, T, V, r, B, s0, s1)) return;
-    // the hull includes the block's inner hole r < r_A: split the interval
-    // there so the walk covers the block cells only
-    float pa0 = s0, pa1 = s1, pb0 = 1.0f, pb1 = 0.0f;
-    if (T.r[B.rA].x > 0.0f) {
-        if (r.flags & RAY_AXIAL) {
-            const float2 rt = T.r[B.rA];
-            if ((rt.x - r.b) + (rt.y - r.blo) > 0.0f) return;
-        } else {
-            const float wA = shell_w(T.r[B.rA], r);
-            if (wA >= 0.0f) {
-                pa1 = fminf(s1, -wA);
-                pb0 = fmaxf(s0, wA);
-                pb1 = s1;
-            }
-        }
-    }
-    // Walk the first non-empty piece first: most rays that meet the hole have
-    // only the piece after it, and a ray with two pieces is rare (nearly
-    // tangent to r_A within the wedge), so the second walk is then skipped by
-    // whole waves instead of idling every lane whose piece came first.
-    if (!(pa1 > pa0)) {
-        pa0 = pb0;
-        pa1 = pb1;
-        pb0 = 1.0f;
-        pb1 = 0.0f;
-    }
-    // The walk is boxed to the block, so every visited cell has a slot:
-    // slot = h ps + t rs + q - (hA ps + tA rs + rA), folded into the bases.
-    const int rs = (B.rB - B.rA) + 1;
-    const int ps = (B.tB - B.tA) * rs + 1;
-    const int off = B.hA * ps + B.tA * rs + B.rA;
+__device__ __forceinline__ void bp_ray(const GeomDev &g, const Tabs &T, const Frame &F, const ViewDev &V,
+                                       const Block &B, int u, int v, float yj, unsigned long long *acc64,
+                                       float nscale) {
+    // slot of cell (h, t, q) = h ps + t rs + q - (hA ps + (tA - 1) rs + rA)
+    // (see slot), clamped into the accumulator
+    const int rs = slot_rs(B), ps = slot_ps(B);
+    const int off = B.hA * ps + (B.tA - 1) * rs + B.rA;
     struct Scatter {
         unsigned long long *b64;
-        int ps, rs;
+        int ps, rs, off, last;
         float yj, nscale;
         __device__ __forceinline__ void operator()(int h, int t, int q, float len) {
-            const int loc = (int)(__umul24(h, ps) + __umul24(t, rs)) + q;
+            const unsigned loc = min((unsigned)((int)(__umul24(h, ps) + __umul24(t, rs)) + q - off), (unsigned)last);
             const unsigned int c = (unsigned int)round_half_up(len * yj);
             const unsigned int n = (unsigned int)round_half_up(len * nscale);
             atomicAdd(&b64[loc], ((unsigned long long)c << 32) | n);
         }
-        __device__ __forceinline__ void late() {}
-    } visit{acc64 - off, ps, rs, yj, nscale};
-    const Box bx{B.hA, B.hB - B.hA, B.tA, B.tB - B.tA, B.rA, B.rB - B.rA};
-    for (int piece = 0; piece < 2; ++piece) {
-        const float a0 = piece ? pb0 : pa0, a1 = piece ? pb1 : pa1;
-        if (!(a1 > a0)) continue;
-        int ih, it, ir;
-        cell_at(g, r, a0, ih, it, ir);
-        ih = ih < B.hA ? B.hA : (ih >= B.hB ? B.hB - 1 : ih);
-        ir = ir < B.rA ? B.rA : (ir >= B.rB ? B.rB - 1 : ir);
-        if (it < B.tA || it >= B.tB) {
-            // nearest block edge on the circle
-            int dlo = B.tA - it;
-            if (dlo < 0) dlo += g.n_theta;
-            int dhi = it - (B.tB - 1);
-            if (dhi < 0) dhi += g.n_theta;
-            it = dlo <= dhi ? B.tA : B.tB - 1;
-        }
-        traverse<true, PART>(g, T, V, r, a0, a1, ih, it, ir, bx, visit);
-    }
-}
-
-
-// Super-block of the back-projection: sbb = 4 or 8 blocks of the
-// decomposition merged by factors ft (theta) x fr (r) x fh (h) = sbb.  Merging
-// in theta and r cuts the pixels that must be set up more than merging in h
-// (rays are nearly level): on 256x720x128, 4.3 M (ray, block) pairs per view
-// for 2 x 2 x 1 against 6.0 M for 4 blocks stacked in h and 7.1 M for single
-// blocks; h takes the rest of the factor.  The merged wedge stays within pi
-// (the hull clip takes it as the intersection of two half-planes) or covers
-// the whole circle.  sbb blocks' slots always hold the merged block's, with
-// words to spare.
-// A super-block merges sbb = 4 or 8 blocks; its workgroup has one wave per
-// block (64 sbb lanes).
-
-struct SbShape {
-    int fh, ft, fr, nsh, nst, nsr;
-};
-
-__host__ __device__ __forceinline__ SbShape sb_shape(const GeomDev &g, int sbb) {
-    SbShape s;
-    s.ft = (g.nbt >= 2 && 2 * g.bt <= g.n_theta / 2) ? 2 : 1;
-    s.fr = g.nbr >= 2 ? 2 : 1;
-    s.fh = sbb / (s.ft * s.fr);
-    s.nsh = (g.nbh + s.fh - 1) / s.fh;
-    s.nst = (g.nbt + s.ft - 1) / s.ft;
-    s.nsr = (g.nbr + s.fr - 1) / s.fr;
-    return s;
-}
-
-// Sector-edge entries a super-block stages in LDS: its wedge's edges, at most
-// ft bt + 1.
-__host__ __device__ __forceinline__ int sb_edge_words(const GeomDev &g, const SbShape &sb) {
-    return sb.ft * g.bt + 1;
+    } visit{acc64, ps, rs, off, block_slots(B) - 1, yj, nscale};
+    walk_block_ray(g, T, F, V, B, u, v, visit);
 }
 
 // Bound on the length of a ray inside one cell of block B (the cell's
@@ -1212,10 +569,8 @@ __device__ float2 plain_scales(const GeomDev &g, const Tabs &T, const Block &B, 
 // vol += lam * wv * c / n where n > 0.  Plain transpose: y holds the caller's
 // projections (type PT, [n_views][rows][cols]), each cell accumulates c alone
 // (n scale 0) and vol = (accumulate ? vol : 0) + c for every cell.
-// PART: stage only the super-block's sector edges (a grid whose full edge
-// table would leave room for fewer than 4 workgroups per CU); otherwise the
-// whole table, read without the clamp.
-template <int VT, int PT, bool SART, bool PART, int SBB>
+// The walks run in the super-block's frame (block_frame).
+template <int VT, int PT, bool SART, int SBB>
 __device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
     const BpItem &item = L.item[blockIdx.y];
     if ((int)blockIdx.x >= item.nwg) return;
@@ -1229,7 +584,6 @@ __device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
     const int32_t *__restrict__ vlist = item.views;
     extern __shared__ float2 smem[];
     Tabs T;
-    if (!PART) T = stage_tables(g, smem, false);
     const int lane = threadIdx.x & 63;
     // super-blocks: outer rings first (their blocks carry the most work)
     constexpr int nthr = 64 * SBB;
@@ -1247,17 +601,21 @@ __device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
     B.rB = min(B.rA + sb.fr * g.br, g.n_r);
     const int wt = B.tB - B.tA, wr = B.rB - B.rA;
     const int ncell = (B.hB - B.hA) * wt * wr;
-    // the walks are boxed to the super-block, so they read the sector edges
-    // tA .. tB only: PART stages just those (sb_edge_words entries at most),
-    // else the whole table (staged above); then the accumulator words
-    if (PART) T = stage_edges(g, smem, B.tA, B.tB);
-    unsigned long long *acc64 =
-        (unsigned long long *)(smem + (PART ? sb_edge_words(g, sb) : table_floats2(g, false)));
-    // The allocation holds sbb blocks of bh slabs plus one spare word each:
-    // sbb (bh bt br + bh bt + bh + 1) words, at least 3 more than the
-    // super-block's (fh bh)((ft bt)(fr br + 1) + 1) + 1 slots (fh ft fr = sbb,
-    // fh ft <= sbb, fh <= sbb).  Word nslot holds the batch counter, the next two
-    // the fixed-point scales.
+    // the walks are boxed to the super-block, so they read its sector edges
+    // (and one either side) only; then the accumulator words
+    int mfr;
+    const Frame F = block_frame(g, B, mfr);
+    const int nedge = B.tB - B.tA + 3;
+    for (int j = threadIdx.x; j < nedge; j += nthr) smem[j] = block_edge(g, B, mfr, j);
+    T.r = g.r_tab;
+    T.h = g.h_tab;
+    T.cs = smem;
+    T.cs_lo = B.tA - 1;
+    T.cs_n = nedge - 1;
+    unsigned long long *acc64 = (unsigned long long *)(smem + sb_edge_words(g, sb));
+    // The allocation (bp_lds_bytes) holds the block_slots of a full-size
+    // super-block and 4 words more: word nslot holds the batch counter, the
+    // next two the fixed-point scales.
     const int nslot = block_slots(B);
     unsigned int *counter = (unsigned int *)(acc64 + nslot);
     float *scales = (float *)(acc64 + nslot + 1);
@@ -1318,7 +676,7 @@ __device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
             const float yj = SART ? rho[(size_t)(k - view_begin) * npv + (size_t)v * g.cols + u]
                                   : Store<PT>::ld(item.y, (size_t)k * npv + (size_t)v * g.cols + u);
             if (SART || yj != 0.0f)
-                bp_ray<PART>(g, T, g.views[view], B, u, v, yj * cscale, acc64, nscale);
+                bp_ray(g, T, F, g.views[view], B, u, v, yj * cscale, acc64, nscale);
         }
     }
     __syncthreads();
@@ -1348,7 +706,7 @@ __device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
             const size_t gi = ((size_t)(B.hA + h) * g.n_theta + (B.tA + t)) * g.n_r + (B.rA + q);
             const float c = (float)(int)(unsigned int)(a >> 32) * inv_cscale;
             const float w = vw ? ld_any(vw, vwt, gi) : 1.0f;
-            float m = Store<VT>::ld(vol, gi) + lam * w * c / n;
+            float m = Store<VT>::ld(vol, gi) + lam * w * c * frcp(n);
             if (nonneg && m < 0.0f) m = 0.0f;
             Store<VT>::st(vol, gi, m);
         }
@@ -1356,15 +714,15 @@ __device__ __forceinline__ void superblock_bp(const BpLaunch &L) {
 }
 
 // SART update (Eq. 7 over the update's views) on super-blocks.
-template <int VT, bool PART, int SBB>
-__global__ __launch_bounds__(64 * SBB, PART ? 4 : 1) void sart_bp_kernel(const BpLaunch L) {
-    superblock_bp<VT, CYL_F32, true, PART, SBB>(L);
+template <int VT, int SBB>
+__global__ __launch_bounds__(64 * SBB, 4) void sart_bp_kernel(const BpLaunch L) {
+    superblock_bp<VT, CYL_F32, true, SBB>(L);
 }
 
 // Plain transpose A^T y over views [view_begin, view_end) on super-blocks.
-template <int VT, int PT, bool PART, int SBB>
-__global__ __launch_bounds__(64 * SBB, PART ? 4 : 1) void bp_kernel(const BpLaunch L) {
-    superblock_bp<VT, PT, false, PART, SBB>(L);
+template <int VT, int PT, int SBB>
+__global__ __launch_bounds__(64 * SBB, 4) void bp_kernel(const BpLaunch L) {
+    superblock_bp<VT, PT, false, SBB>(L);
 }
 
 // ------------------------------------------------------------ elementwise
@@ -1402,32 +760,25 @@ int launch_record(const cyl_geom *G, int view, const int32_t *rowptr, int32_t *c
     return launch_check("record");
 }
 
-// LDS of a super-block launch: the sector edges (the whole table, or the
-// super-block's part) and 64-bit accumulator words for sbb blocks of bh slabs
-// plus one spare word each (the super-block's slots, its batch counter and its
-// two scale words fit in these).
-static size_t bp_lds_bytes(const GeomDev &g, bool part, int sbb) {
-    const size_t edges = part ? (size_t)sb_edge_words(g, sb_shape(g, sbb)) : (size_t)g.n_theta + 1;
-    return sizeof(float2) * edges +
-           sizeof(unsigned long long) * sbb * (size_t)(g.bh * (g.bt * (g.br + 1) + 1) + 1);
+// LDS of a super-block launch: the super-block's sector edges, then the
+// 64-bit accumulator words of its largest super-block (block_slots of
+// fh bh slabs, ft bt sectors and fr br rings), its batch counter and two
+// scale words, and one word to spare.
+static size_t bp_lds_bytes(const GeomDev &g, int sbb) {
+    const SbShape sb = sb_shape(g, sbb);
+    const size_t slots = (size_t)(sb.fh * g.bh) * ((size_t)(sb.ft * g.bt + 2) * (sb.fr * g.br + 1) + 1) + 1;
+    return sizeof(float2) * (size_t)sb_edge_words(g, sb) + sizeof(unsigned long long) * (slots + 4);
 }
 
-// LDS per workgroup of sbb waves that lets 16 waves (4 per SIMD) share a CU's
-// 160 KiB.
-static size_t lds_for_4(int sbb) { return (size_t)160 * 1024 * sbb / 16; }
-
-// Blocks per super-block of a grid: 8 when the grid has at most 2^25 cells,
-// stages the whole sector-edge table and still gives at least 8 super-blocks
-// per CU (2048); else 4.  Measured per view: 8 took the 256x720x128 update
-// (2944 super-blocks) from 0.403 to 0.388 ms, unposed and posed alike; 4 kept
-// the 512x1440x256 posed one at 3.05 ms against 3.61, the 32x512x256 one
-// (512 super-blocks) at 0.295 against 0.333 and the 32x1608x256 one (partial
-// table) at 0.479 against 0.485.  A property of the grid alone, so a scan's
-// result does not depend on the batch it is launched with; a launch holds
-// items of one size, and only 4-block launches stage partial tables.
+// Blocks per super-block of a grid: 8 when the grid has at most 2^25 cells
+// and still gives at least 8 super-blocks per CU (2048); else 4.  Measured per
+// view: 8 took the 256x720x128 update (2944 super-blocks) from 0.403 to 0.388
+// ms, unposed and posed alike; 4 kept the 512x1440x256 posed one at 3.05 ms
+// against 3.61 and the 32x512x256 one (512 super-blocks) at 0.295 against
+// 0.333.  A property of the grid alone, so a scan's result does not depend on
+// the batch it is launched with; a launch holds items of one size.
 static int grid_sbb(const GeomDev &g) {
     if ((int64_t)g.n_h * g.n_theta * g.n_r > ((int64_t)1 << 25)) return 4;
-    if (bp_lds_bytes(g, false, 8) > lds_for_4(8)) return 4;
     const SbShape sb = sb_shape(g, 8);
     return (int64_t)sb.nsh * sb.nst * sb.nsr >= 2048 ? 8 : 4;
 }
@@ -1483,7 +834,6 @@ static BpItem bp_item(const cyl_geom *G, const void *y, int vb, int ve, void *vo
 struct LaunchShape {
     int maxwg = 0;
     size_t lds = 0;
-    bool part = false;  // BP: super-blocks stage only their own sector edges
     int sbb = 4;        // BP: blocks per super-block (and waves per workgroup)
 };
 
@@ -1579,21 +929,17 @@ static void store_i32(int32_t *dst, const int32_t *src, int n, hipStream_t st) {
 template <int VT, int PT>
 static void launch_bp_t(const BpLaunch &L, const LaunchShape &sh, bool sart, hipStream_t st) {
     dim3 grid(sh.maxwg, L.n);
-#define CYL_BP_LAUNCH(PART, SBB)                                                                      \
-    do {                                                                                              \
-        if (sart)                                                                                     \
-            hipLaunchKernelGGL((sart_bp_kernel<VT, PART, SBB>), grid, dim3(64 * SBB), sh.lds, st, L); \
-        else                                                                                          \
-            hipLaunchKernelGGL((bp_kernel<VT, PT, PART, SBB>), grid, dim3(64 * SBB), sh.lds, st, L);  \
+#define CYL_BP_LAUNCH(SBB)                                                                      \
+    do {                                                                                        \
+        if (sart)                                                                               \
+            hipLaunchKernelGGL((sart_bp_kernel<VT, SBB>), grid, dim3(64 * SBB), sh.lds, st, L); \
+        else                                                                                    \
+            hipLaunchKernelGGL((bp_kernel<VT, PT, SBB>), grid, dim3(64 * SBB), sh.lds, st, L);  \
     } while (0)
-    if (sh.sbb == 8) {
-        CYL_BP_LAUNCH(false, 8);
-    } else {
-        if (sh.part)
-            CYL_BP_LAUNCH(true, 4);
-        else
-            CYL_BP_LAUNCH(false, 4);
-    }
+    if (sh.sbb == 8)
+        CYL_BP_LAUNCH(8);
+    else
+        CYL_BP_LAUNCH(4);
 #undef CYL_BP_LAUNCH
 }
 
@@ -1626,10 +972,9 @@ static void launch_bp_batch(const BpLaunch &L, const cyl_geom *const *geoms, int
             g2[L2.n] = geoms[i];
             L2.item[L2.n++] = it;
             sh.maxwg = std::max(sh.maxwg, it.nwg);
-            sh.part = sh.part || bp_lds_bytes(geoms[i]->dev, false, sbb) > lds_for_4(sbb);  // never for 8
         }
         if (L2.n == 0) continue;
-        for (int i = 0; i < L2.n; ++i) sh.lds = std::max(sh.lds, bp_lds_bytes(g2[i]->dev, sh.part, sbb));
+        for (int i = 0; i < L2.n; ++i) sh.lds = std::max(sh.lds, bp_lds_bytes(g2[i]->dev, sbb));
         switch (vt) {
             case CYL_F32: launch_bp_v<CYL_F32>(L2, sh, pt, sart, st); break;
             case CYL_F16: launch_bp_v<CYL_F16>(L2, sh, pt, sart, st); break;
@@ -1736,7 +1081,7 @@ extern "C" int cyl_row_sums(const cyl_geom *G, float *out, int32_t view_begin, i
     }
     const GeomDev &g = G->dev;
     dim3 grid(((g.cols + 15) / 16) * ((g.rows + 15) / 16), view_end - view_begin);
-    hipLaunchKernelGGL(rowsum_kernel, grid, dim3(256), table_bytes(g), (hipStream_t)hip_stream, g, out, view_begin);
+    hipLaunchKernelGGL(rowsum_kernel, grid, dim3(256), 0, (hipStream_t)hip_stream, g, out, view_begin);
     return launch_check("cyl_row_sums");
 }
 

@@ -153,7 +153,7 @@ def test_batch_of_more_than_16_and_oracle(torch_cuda):
                          vox_weights=j.w_host.astype(np.float32).astype(np.float64))
         e = rel_l2(host(j.vol), want)
         say(j.name, "rel L2 vs oracle %.2e" % e)
-        assert e <= 1e-4
+        assert e <= 1.5e-6  # measured at most 1.1e-7
 
 
 def test_batch_rejects_bad_items(torch_cuda):

@@ -54,7 +54,7 @@ def test_os_tiny_matches_oracle(torch_cuda, subset):
     scan = cfg["scan"]
     ph = I.tiny_phantom(scan.grid, cfg["seed"])
     errs = _os_pair(scan, ph, 6, subset, False, False, label="tiny")
-    assert max(errs) <= 1e-4
+    assert max(errs) <= 1.5e-5  # measured at most 1.5e-6
 
 
 def test_os_weighted_posed_ragged_groups_matches_oracle(torch_cuda):
@@ -64,14 +64,14 @@ def test_os_weighted_posed_ragged_groups_matches_oracle(torch_cuda):
     ph = I.industrial_phantom(scan.grid, 1002, n_annuli=5, n_incl=6)
     order = np.random.default_rng(4410).permutation(scan.n_views).astype(np.int32)
     errs = _os_pair(scan, ph, 3, 5, True, True, order=order, label="scaled weighted os5")
-    assert max(errs) <= 1e-4
+    assert max(errs) <= 7e-7  # measured 6.7e-8
 
 
 def test_sirt_scaled_matches_oracle(torch_cuda):
     scan = I.scaled_single(n_h=32, n_theta=96, n_r=24, n_views=24, det=64)
     ph = I.industrial_phantom(scan.grid, 1003, n_annuli=5, n_incl=6)
     errs = _os_pair(scan, ph, 3, scan.n_views, True, True, label="scaled sirt")
-    assert max(errs) <= 1e-4
+    assert max(errs) <= 3e-7  # measured 2.9e-8
 
 
 def test_os_subset_one_is_sart_and_resume_bitwise(torch_cuda):
