@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP16/BF16 storage measurement")
     ap.add_argument("--kernel-views", type=int, default=120,
                     help="views in the per-kernel HIP-event timing pass")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -337,13 +338,28 @@ def symmetric_matrix(G, scan, p, prior, w, lam, truth):
     return out
 
 
+def cpu_info():
+    """Host CPU model and core counts (for the CPU baseline's record)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(scan, truth, prior, weights, p, nthreads):
     """The FP64 oracle (test infrastructure) on a bounded sample: one SART
-    sub-iteration (FP + residual + BP + update) for 6 of the 120 views (about
-    13 s on 16 host threads), scaled to SART iterations/s."""
+    sub-iteration (FP + residual + BP + update) for 8 of the 120 views
+    (k = 0, 15, ..., 105; about 15 s on 16 host threads), scaled to SART
+    iterations/s."""
     from oracle import ref
     o = ref.Oracle(scan)
-    sample_views = [0, 20, 40, 60, 80, 100]
+    sample_views = list(range(0, 120, 15))
     t0 = time.perf_counter()
     P = scan.det_rows * scan.det_cols
     mu = prior.astype(np.float64).ravel().copy()
@@ -359,10 +375,80 @@ def cpu_baseline(scan, truth, prior, weights, p, nthreads):
     dt = time.perf_counter() - t0
     per_view = dt / len(sample_views)
     it_s = 1.0 / (per_view * scan.n_views)
-    return {"value": it_s, "unit": "SART it/s", "cores": nthreads, "kind": "oracle",
-            "sample": "%d of %d views (one SART sub-iteration each, %.1f s), scaled x%d"
-                      % (len(sample_views), scan.n_views, dt, scan.n_views / len(sample_views)),
-            "seconds": dt}
+    out = {"value": it_s, "unit": "SART it/s", "cores": nthreads, "kind": "oracle",
+           "sample": "%d of %d views (k = 0, 15, ..., 105; one SART sub-iteration each, %.1f s), scaled x%d"
+                     % (len(sample_views), scan.n_views, dt, scan.n_views / len(sample_views)),
+           "seconds": dt,
+           "threads_note": "the oracle's own threads, capped at the 16 host threads a one-GPU job is given"}
+    out.update(cpu_info())
+    return out
+
+
+def mixed_precision(cfg, ph, p32, nthreads, steps=3):
+    """FP16 and BF16 storage (Eq. 7 with the volume, data and weights stored in
+    16 bits, FP32 arithmetic): SART it/s on the full 256x720x128 scan, and the
+    relative L2 distance to the FP64 oracle's iterates after each of 2
+    iterations over 12 of its views (every 10th), from the same prior and on
+    the same data (the FP32 projections the bench measures with), FP32
+    alongside."""
+    import torch
+    from oracle import ref
+    from paper_2005_11976_amd import cyl, inputs as I
+    scan = cfg["scan"]
+    lam = cfg["lam"]
+    out = {}
+    # rates on the full scan
+    G = cyl.Geometry(scan, 0)
+    ws = torch.empty(G.workspace_bytes(), dtype=torch.uint8, device="cuda")
+    for name, tdt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
+        p = p32.to(tdt).contiguous()
+        prior = torch.from_numpy(ph.prior.astype(np.float32)).cuda().to(tdt).contiguous()
+        w = torch.from_numpy(ph.weights.astype(np.float32)).cuda().to(tdt).contiguous()
+        vol = prior.clone()
+        G.sart(p, vol, 1, lam, vox_weights=w, workspace=ws)
+        vol.copy_(prior)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for s in range(steps):
+            G.sart(p, vol, s + 1, lam, vox_weights=w, workspace=ws, start_iter=s)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = {"value": 1000.0 * steps / e0.elapsed_time(e1), "unit": "SART it/s"}
+        log("mixed %s: %.3f SART it/s" % (name, out[name]["value"]))
+    del ws
+    # accuracy against the FP64 oracle on 12 views
+    sub = I.Scan(scan.grid, scan.views[::10], scan.det_rows, scan.det_cols, scan.R, scan.T)
+    data = p32[::10].contiguous()
+    data64 = data.cpu().numpy().astype(np.float64)
+    wts = ph.weights.astype(np.float32)
+    mu = ph.prior.astype(np.float32).astype(np.float64)
+    ref_iters = []
+    t0 = time.perf_counter()
+    for it in range(2):
+        for k in range(sub.n_views):
+            one = I.Scan(sub.grid, sub.views[k:k + 1], sub.det_rows, sub.det_cols, sub.R, sub.T)
+            mu, _ = ref.Oracle(one).sart(data64[k:k + 1], mu, 1, lam, vox_weights=wts, nthreads=nthreads)
+        ref_iters.append(mu.copy())
+    log("mixed: oracle iterates (12 views x 2) in %.1f s" % (time.perf_counter() - t0))
+    Gs = cyl.Geometry(sub, 0)
+    for name, tdt in (("f32", torch.float32), ("f16", torch.float16), ("bf16", torch.bfloat16)):
+        p = data.to(tdt).contiguous()
+        vol = torch.from_numpy(ph.prior.astype(np.float32)).cuda().to(tdt).contiguous()
+        w = torch.from_numpy(wts).cuda().to(tdt).contiguous()
+        errs = []
+        for it in range(2):
+            Gs.sart(p, vol, it + 1, lam, vox_weights=w, start_iter=it)
+            got = vol.float().cpu().numpy().astype(np.float64).ravel()
+            want = np.ravel(ref_iters[it])
+            errs.append(float(np.linalg.norm(got - want) / np.linalg.norm(want)))
+        out.setdefault(name, {})
+        out[name]["rel_l2_vs_fp64_oracle"] = errs
+        out[name]["final_rel_l2_vs_fp64_oracle"] = errs[-1]
+        log("mixed %s: rel L2 vs FP64 oracle per iteration %s" % (name, " ".join("%.3e" % e for e in errs)))
+    out["accuracy_run"] = "256x720x128 grid, 12 of the 120 views (every 10th), 2 weighted SART iterations from the prior"
+    out["storage"] = "volume, projections and voxel weights in the named type; FP32 arithmetic and residual images"
+    return out
 
 
 def main():
@@ -479,9 +565,12 @@ def main():
     large_out = None if args.core_only or args.dtype != "f32" else posed_large()
     serving_out = serving(args) if args.serve_requests > 0 and not args.core_only else None
 
+    nthreads = max(1, min(16, len(os.sched_getaffinity(0))))
+    mixed_out = None
+    if not args.core_only and not args.no_mixed and args.dtype == "f32":
+        mixed_out = mixed_precision(cfg, ph, p32, nthreads)
     cpu = None
     if not args.no_cpu_baseline:
-        nthreads = max(1, min(16, len(os.sched_getaffinity(0))))
         log("cpu baseline (oracle) on", nthreads, "threads")
         cpu = cpu_baseline(scan, ph.truth, ph.prior, ph.weights, p32.cpu().numpy(), nthreads)
         log("cpu baseline %.5f it/s" % cpu["value"])
@@ -511,6 +600,7 @@ def main():
                      "bytes_per_launch": dom_bytes},
         "valu": valu,
         "cpu_baseline": cpu,
+        "mixed": mixed_out,
         "ordered_subsets": os_out,
         "comparison_projectors": cmp_out,
         "symmetric_matrix": sym_out,

@@ -187,9 +187,11 @@ __device__ __forceinline__ void walk_block_ray(const GeomDev &g, const Tabs &T, 
             it = dlo <= dhi ? B.tA : B.tB - 1;
         }
         if (B.tB - B.tA >= g.n_theta)
-            traverse<true, true, true>(g, T, V, r, a0, a1, ih, it, ir, visit);
+            traverse<true, true, true, true>(g, T, V, r, a0, a1, ih, it, ir, visit);
+        else if (__ballot(needs_refine(r, a0, a1)))
+            traverse<false, true, true, true>(g, T, V, r, a0, a1, ih, it, ir, visit);
         else
-            traverse<false, true, true>(g, T, V, r, a0, a1, ih, it, ir, visit);
+            traverse<false, true, true, false>(g, T, V, r, a0, a1, ih, it, ir, visit);
     }
 }
 

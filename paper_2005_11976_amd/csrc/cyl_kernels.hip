@@ -126,7 +126,7 @@ static_assert(sizeof(FpLaunch) <= 4096 && sizeof(BpLaunch) <= 4096, "kernel argu
 // Partial forward projection of piece `piece` of `npieces` equal parameter
 // ranges of ray (u, v): each piece starts from its own cell so the pieces of
 // one ray can run on neighbouring lanes.
-template <int VT, bool PRECISE>
+template <int VT, bool PRECISE, bool REFINE>
 __device__ __forceinline__ float fp_piece(const GeomDev &g, const Tabs &T, const ViewDev &V, const Frame &F,
                                           const Ray &r, __amdgpu_buffer_rsrc_t vol, int piece, int npieces) {
     if (!(r.flags & RAY_HIT)) return 0.0f;
@@ -146,8 +146,10 @@ __device__ __forceinline__ float fp_piece(const GeomDev &g, const Tabs &T, const
         float acc, plen, pval;
         __device__ __forceinline__ void operator()(int h, int t, int q, float len) {
             // a slab index outside the grid (a step of rounding past its end
-            // faces) addresses past the volume, where the buffer load reads 0
-            const unsigned idx = __umul24(min((unsigned)h, (unsigned)nh), ntr) + __umul24(t, nr) + (q < 0 ? 0 : q);
+            // faces) addresses past the volume, where the buffer load reads 0;
+            // the hole (q = -1) reads a neighbouring word (or past the volume)
+            // and weighs it by 0
+            const unsigned idx = __umul24(min((unsigned)h, (unsigned)nh), ntr) + __umul24(t, nr) + q;
             // kept in place (volatile) so the compiler neither sinks it to the end
             // of the step nor copies the loaded value
             asm volatile("v_fmac_f32 %0, %1, %2" : "+v"(acc) : "v"(plen), "v"(pval));
@@ -155,7 +157,7 @@ __device__ __forceinline__ float fp_piece(const GeomDev &g, const Tabs &T, const
             plen = q < 0 ? 0.0f : len;
         }
     } visit{vol, g.n_h, g.n_theta, g.n_r, g.n_theta * g.n_r, 0.0f, 0.0f, 0.0f};
-    traverse<true, false, PRECISE>(g, T, V, r, a0, a1, ih, it, ir, visit);
+    traverse<true, false, PRECISE, REFINE>(g, T, V, r, a0, a1, ih, it, ir, visit);
     return fmaf(visit.plen, visit.pval, visit.acc);
 }
 
@@ -200,11 +202,17 @@ __global__ __launch_bounds__(256) void fp_kernel(const FpLaunch L) {
     const __amdgpu_buffer_rsrc_t vrs =
         buffer_rsrc(vol, (unsigned)g.n_h * (unsigned)g.n_theta * (unsigned)g.n_r * (unsigned)Store<VT>::kSize);
     // rays whose reference point lies far from their closest approach (nearly
-    // parallel to the axis) need the shell roots as small differences; a
-    // wave-wide choice
+    // parallel to the axis) need the shell roots as small differences, and
+    // rays passing near the axis may need FP64 edge crossings; wave-wide
+    // choices
     const bool far_ref = (r.flags & RAY_HIT) && (r.k2 < 0.25f || fabsf(r.sc) > (float)g.r_max_d);
-    float acc = __ballot(far_ref) ? fp_piece<VT, true>(g, T, V, F, r, vrs, piece, nsplit)
-                                  : fp_piece<VT, false>(g, T, V, F, r, vrs, piece, nsplit);
+    float acc;
+    if (__ballot(far_ref))
+        acc = fp_piece<VT, true, true>(g, T, V, F, r, vrs, piece, nsplit);
+    else if (__ballot(needs_refine(r, r.s_in, r.s_out)))
+        acc = fp_piece<VT, false, true>(g, T, V, F, r, vrs, piece, nsplit);
+    else
+        acc = fp_piece<VT, false, false>(g, T, V, F, r, vrs, piece, nsplit);
     if (nsplit > 1) {
         part[threadIdx.x] = acc;
         __syncthreads();
@@ -271,7 +279,7 @@ __global__ __launch_bounds__(256) void record_kernel(GeomDev g, int view, int fi
     if ((r.flags & RAY_HIT) && r.s_out > r.s_in) {
         int ih, it, ir;
         cell_at(g, r, F, r.s_in, ih, it, ir);
-        traverse<true, false, true>(g, T, V, r, r.s_in, r.s_out, ih, it, ir, rec);
+        traverse<true, false, true, true>(g, T, V, r, r.s_in, r.s_out, ih, it, ir, rec);
     }
     if (!fill) {
         counts[pix] = rec.n;

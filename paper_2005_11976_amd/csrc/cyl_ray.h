@@ -212,7 +212,13 @@ __device__ __forceinline__ float plane_s(float2 ht, const Ray &r) {
 // quotient is ill-conditioned); c = (cos, sin) of the edge in the object
 // frame.  on_edge: the meeting lies on the edge's half-line.
 __device__ __forceinline__ void edge_cross_fp64(double2 c, const ViewDev &V, const Ray &r, float &s, bool &on_edge) {
-    const double fu = (double)(r.pix & 0xffff), fv = (double)(r.pix >> 16);
+    // the per-ray inputs pass through an empty asm statement so that the
+    // compiler does not hoist their FP64 forms out of the walk loop (where
+    // they would hold registers on every step for a path that rarely runs)
+    int pix = r.pix;
+    float tref = r.tref, len = r.len;
+    asm volatile("" : "+v"(pix), "+v"(tref), "+v"(len));
+    const double fu = (double)(pix & 0xffff), fv = (double)(pix >> 16);
     const double dx = fma(fv, V.V[0], fma(fu, V.U[0], V.d0[0]));
     const double dy = fma(fv, V.V[1], fma(fu, V.U[1], V.d0[1]));
     const double nd = c.x * dy - c.y * dx;
@@ -225,7 +231,7 @@ __device__ __forceinline__ void edge_cross_fp64(double2 c, const ViewDev &V, con
     const double t = -na / nd;
     const double px = fma(t, dx, V.a[0]), py = fma(t, dy, V.a[1]);
     on_edge = (c.x * px + c.y * py) > 0.0;
-    s = (float)((t - (double)r.tref) * (double)r.len);
+    s = (float)((t - (double)tref) * (double)len);
 }
 
 // Below this |n.e| the FP32 edge quotient is re-solved in FP64 (only rays
@@ -373,17 +379,32 @@ __device__ __forceinline__ float plane_next(const Walk &w, int ih) {
 // s, or +inf.  An edge-half-line meeting behind s means the start cell was
 // one sector short (rounding at entry): cross it at once.  Near-parallel
 // cases (|n.e| below kEdgeTau) whose crossing may fall before s_end are
-// re-solved in FP64 when `refine` is set.
+// re-solved in FP64 when REFINE and `refine` are set (walks that cannot meet
+// such a case, see needs_refine, are compiled without the test).
+template <bool REFINE>
 __device__ __forceinline__ float edge_next(const ViewDev &V, const GeomDev &g, const Walk &w, const Ray &r,
                                            float2 cs, int be, float s, float s_end, bool refine) {
     const float nc = cs.x * w.tpy - cs.y * w.tpx;
     const float ne = cs.x * w.tey - cs.y * w.tex;
     float x = -nc * frcp(ne);
     bool ahead = ne > 0.0f;
-    if (refine && w.dir_t != 0 && fabsf(ne) < kEdgeTau) {
+    if (REFINE && refine && w.dir_t != 0 && fabsf(ne) < kEdgeTau) {
         if (fabsf(nc) <= fabsf(ne) * (s_end - s + 1.0f)) edge_cross_fp64(g.cs64[be], V, r, x, ahead);
     }
     return (w.dir_t != 0 && ahead) ? vmax(x, s) : CYL_INF;
+}
+
+// Whether a walk of the ray over [s0, s1] may meet an edge crossing that
+// edge_next re-solves in FP64.  The crossing of edge b at distance rho_b from
+// the axis has |n_b . e| = kappa b / rho_b, and a crossing that the test
+// considers (|sigma| <= s1 - s0 + 1) lies within r0 + kappa (s1 - s0 + 1) of
+// the axis; so |n_b . e| < kEdgeTau needs kappa b below kEdgeTau times that
+// radius (taken with a margin of 1 %).
+__device__ __forceinline__ bool needs_refine(const Ray &r, float s0, float s1) {
+    if ((r.flags & (RAY_AXIAL | RAY_THRU)) || !(r.flags & RAY_HIT)) return false;
+    const float kappa = fsqrt(r.k2);
+    const float rho = r.r0 + kappa * (s1 - s0 + 1.0f) + 1.0f;
+    return kappa * r.b < 1.01f * kEdgeTau * rho;
 }
 
 // Walk the ray from s to s_end starting in cell (ih, it, ir) and call
@@ -400,7 +421,7 @@ __device__ __forceinline__ float edge_next(const ViewDev &V, const GeomDev &g, c
 // rounding at its faces (visitors clamp what they index).  WRAP: the sector
 // index wraps around the circle (walks whose region is the whole circle);
 // CLAMP: the edge table holds only the region's edges.
-template <bool WRAP, bool CLAMP, bool PRECISE, class Visit>
+template <bool WRAP, bool CLAMP, bool PRECISE, bool REFINE, class Visit>
 __device__ __forceinline__ void traverse(const GeomDev &g, const Tabs &T, const ViewDev &V, const Ray &r, float s,
                                          const float s_end, int ih, int it, int ir, Visit &visit) {
     const int nt = g.n_theta;
@@ -437,7 +458,12 @@ __device__ __forceinline__ void traverse(const GeomDev &g, const Tabs &T, const 
     if (r.flags & RAY_THRU)
         s_t = s < r.sc ? r.sc : CYL_INF;
     else
-        s_t = edge_next(V, g, w, r, edge_at<CLAMP>(T, it + w.up_t), it + w.up_t, s, s_end, true);
+        s_t = edge_next<true>(V, g, w, r, edge_at<CLAMP>(T, it + w.up_t), it + w.up_t, s, s_end, true);
+    // the edge ahead of sector it is entry it + up_t of the table (it + up_t -
+    // cs_lo of a partial table, clamped into it)
+    const int cofs = w.up_t - (CLAMP ? T.cs_lo : 0);
+    const float2 *__restrict__ csb = T.cs + cofs;
+    // a guard on the step count (the walk ends at s_end on its own)
     const int max_steps = 2 * g.n_r + nt + g.n_h + 8;
     for (int n = 0; n < max_steps; ++n) {
         const float sn = vmin(vmin3(s_z, s_r, s_t), s_end);
@@ -447,7 +473,7 @@ __device__ __forceinline__ void traverse(const GeomDev &g, const Tabs &T, const 
         int itn = it + (ev_t ? w.tstep : 0);
         if (WRAP) itn -= ((unsigned)itn >= (unsigned)nt) ? w.twrap : 0;
         const int be = itn + w.up_t;
-        const float2 cse = edge_at<CLAMP>(T, be);
+        const float2 cse = CLAMP ? T.cs[min((unsigned)(itn + cofs), (unsigned)T.cs_n)] : csb[itn];
         visit(ih, it, ir, sn - s);
         s = sn;
         ih += ev_z ? w.dir_h : 0;
@@ -457,7 +483,7 @@ __device__ __forceinline__ void traverse(const GeomDev &g, const Tabs &T, const 
         int rd;
         const float nz = plane_next(w, ih);
         const float nrr = shell_next<PRECISE>(g, w, r, ir, s, rd);
-        const float ntt = edge_next(V, g, w, r, cse, be, s, s_end, ev_t);
+        const float ntt = edge_next<REFINE>(V, g, w, r, cse, be, s, s_end, ev_t);
         s_z = ev_z ? nz : s_z;
         s_r = ev_r ? nrr : s_r;
         r_dir = ev_r ? rd : r_dir;
