@@ -28,17 +28,17 @@ HBM_PEAK_GBS = 8000.0
 # device copy, taken on the kernel sources whose sha256 prefix is given here
 # (profiles/fp_bp_sart_single_256x720x128_hbm_counters.md). For any other
 # source, or another storage type, the traffic is reported as null.
-MEASURED_TRAFFIC = {"src_sha": "6f4bf3b48f1a5eac",
-                    "fp_residual": 129199351 + 1317550,
-                    "bp_update": 192700024 + 93193984}
+MEASURED_TRAFFIC = {"src_sha": "be1e93b74c6bdafc",
+                    "fp_residual": 143590000 + 1210163,
+                    "bp_update": 193154000 + 93194035}
 # VALU wave-instructions per launch (rocprofv3 SQ_INSTS_VALU) of the same
 # sources (profiles/fp_bp_sart_single_256x720x128_valu_counters.md).  A wave64
 # VALU instruction takes 4 cycles of a 16-lane SIMD (packed FP32 is off), so
 # the issue capacity of a launch is 1024 SIMDs x 2.4 GHz x duration / 4.
 # active_lanes: SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU), the fraction of
 # the 64 lanes that work in an average VALU instruction.
-MEASURED_VALU = {"src_sha": "6f4bf3b48f1a5eac", "fp_residual": 1.048e8, "bp_update": 2.19e8,
-                 "active_lanes": {"fp_residual": 0.951, "bp_update": 0.709}}
+MEASURED_VALU = {"src_sha": "be1e93b74c6bdafc", "fp_residual": 1.018e8, "bp_update": 2.311e8,
+                 "active_lanes": {"fp_residual": 0.951, "bp_update": 0.696}}
 VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
 
 
