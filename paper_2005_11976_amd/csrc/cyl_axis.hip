@@ -17,16 +17,11 @@
 #include <cstdint>
 
 #include "cyl_internal.h"
+#include "cyl_store.h"
 
 namespace cyl {
 
 namespace {
-
-__device__ __forceinline__ float load_any(const void *p, int dt, size_t i) {
-    if (dt == CYL_F32) return ((const float *)p)[i];
-    if (dt == CYL_F16) return __half2float(((const __half *)p)[i]);
-    return __uint_as_float((uint32_t)((const uint16_t *)p)[i] << 16);
-}
 
 __device__ __forceinline__ uint64_t pack(uint32_t key, uint32_t tie) { return ((uint64_t)key << 32) | tie; }
 
@@ -96,7 +91,7 @@ __global__ __launch_bounds__(kCornerThreads) void axis_corner_kernel(const void 
 #pragma unroll
         for (int q = 0; q < kCornerLoads; ++q) {
             const size_t jq = j + (size_t)q * kCornerThreads;
-            val[q] = jq < npix ? load_any(proj, PT, base + jq) : threshold;
+            val[q] = jq < npix ? ld_any(proj, PT, base + jq) : threshold;
         }
 #pragma unroll
         for (int q = 0; q < kCornerLoads; ++q) {
@@ -154,7 +149,7 @@ __global__ __launch_bounds__(256) void side_sum_kernel(const void *__restrict__ 
         const size_t n = (size_t)(b - a + 1) * cols;
         for (size_t j = threadIdx.x; j < n; j += blockDim.x) {
             const int u = (int)(j % cols);
-            const double val = (double)load_any(proj, pt, base + (size_t)a * cols + j);
+            const double val = (double)ld_any(proj, pt, base + (size_t)a * cols + j);
             double f = c - ((double)u - 0.5);
             f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
             left += f * val;

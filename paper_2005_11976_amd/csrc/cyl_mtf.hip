@@ -15,16 +15,11 @@
 #include <cstdint>
 
 #include "cyl_internal.h"
+#include "cyl_store.h"
 
 namespace cyl {
 
 namespace {
-
-__device__ __forceinline__ double load_cell(const void *p, int dt, size_t i) {
-    if (dt == CYL_F32) return (double)((const float *)p)[i];
-    if (dt == CYL_F16) return (double)__half2float(((const __half *)p)[i]);
-    return (double)__uint_as_float((uint32_t)((const uint16_t *)p)[i] << 16);
-}
 
 // One workgroup per output.  window = 0: output r covers ring r (all theta);
 // window = w: output k covers rings [k w, (k + 1) w).
@@ -41,8 +36,8 @@ __global__ __launch_bounds__(256) void mtf_kernel(const void *__restrict__ vol, 
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         const int t = j / nw, r = r0 + j % nw;
         const size_t c = (size_t)t * n_r + r;
-        double x = load_cell(vol, vt, s0 + c);
-        if (two) x = 0.5 * (x + load_cell(vol, vt, s1 + c));
+        double x = (double)ld_any(vol, vt, s0 + c);
+        if (two) x = 0.5 * (x + (double)ld_any(vol, vt, s1 + c));
         hi = fmax(hi, x);
         lo = fmin(lo, x);
     }

@@ -25,32 +25,11 @@
 #include <cstdint>
 
 #include "cyl_internal.h"
+#include "cyl_store.h"
 
 namespace cyl {
 
 namespace {
-
-__device__ __forceinline__ float ld_val(const void *p, int dt, size_t i) {
-    if (dt == CYL_F32) return ((const float *)p)[i];
-    if (dt == CYL_F16) return __half2float(((const __half *)p)[i]);
-    return __uint_as_float((uint32_t)((const uint16_t *)p)[i] << 16);
-}
-
-__device__ __forceinline__ void st_val(void *p, int dt, size_t i, float x) {
-    if (dt == CYL_F32) {
-        ((float *)p)[i] = x;
-    } else if (dt == CYL_F16) {
-        ((__half *)p)[i] = __float2half_rn(x);
-    } else {
-        uint32_t b = __float_as_uint(x);
-        if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x7fffffu)) {
-            ((uint16_t *)p)[i] = (uint16_t)((b >> 16) | 0x40u);  // quiet NaN
-        } else {
-            b += 0x7fffu + ((b >> 16) & 1u);  // round to nearest even
-            ((uint16_t *)p)[i] = (uint16_t)(b >> 16);
-        }
-    }
-}
 
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
 
@@ -131,7 +110,7 @@ __global__ __launch_bounds__(256) void fp_sampled_kernel(const GeomDev g, const 
                 const int ir = clampi((int)floorf((r - g.r_min) * g.inv_dr), 0, g.n_r - 1);
                 const int ih = clampi((int)floorf((z - g.h_min) * g.inv_dh), 0, g.n_h - 1);
                 const int it = clampi((int)floorf(th * g.inv_dtheta), 0, g.n_theta - 1);
-                q += ld_val(vol, VT, ((size_t)ih * g.n_theta + it) * g.n_r + ir);
+                q += ld_any(vol, VT, ((size_t)ih * g.n_theta + it) * g.n_r + ir);
             } else {
                 const float fr = (r - g.r_min) * g.inv_dr - 0.5f;
                 const float fh = (z - g.h_min) * g.inv_dh - 0.5f;
@@ -150,8 +129,8 @@ __global__ __launch_bounds__(256) void fp_sampled_kernel(const GeomDev g, const 
                         it -= it >= g.n_theta ? g.n_theta : 0;
                         const float wtt = dt ? wt : 1.0f - wt;
                         const size_t rowb = ((size_t)ih * g.n_theta + it) * g.n_r;
-                        const float a0 = ld_val(vol, VT, rowb + clampi(r0, 0, g.n_r - 1));
-                        const float a1 = ld_val(vol, VT, rowb + clampi(r0 + 1, 0, g.n_r - 1));
+                        const float a0 = ld_any(vol, VT, rowb + clampi(r0, 0, g.n_r - 1));
+                        const float a1 = ld_any(vol, VT, rowb + clampi(r0 + 1, 0, g.n_r - 1));
                         acc = fmaf(whh * wtt, fmaf(wr, a1 - a0, a0), acc);
                     }
                 }
@@ -163,11 +142,11 @@ __global__ __launch_bounds__(256) void fp_sampled_kernel(const GeomDev g, const 
     q *= sf;
     const size_t o = ((size_t)view * g.rows + v) * g.cols + u;
     if (!SART) {
-        st_val(proj, pt, o, q);
+        st_any(proj, pt, o, q);
     } else {
         const float L = sf * (float)count;
-        const float w = pw ? ld_val(pw, pwt, o) : 1.0f;
-        rho[pix] = L > 0.0f ? w * (ld_val(proj, pt, o) - q) / L : 0.0f;
+        const float w = pw ? ld_any(pw, pwt, o) : 1.0f;
+        rho[pix] = L > 0.0f ? w * (ld_any(proj, pt, o) - q) / L : 0.0f;
     }
 }
 
@@ -211,18 +190,18 @@ __global__ __launch_bounds__(256) void bp_voxel_kernel(const GeomDev g, const vo
                 const int uu = u0 + du;
                 if (uu < 0 || uu >= g.cols) continue;
                 const float w = wv_ * (du ? fu : 1.0f - fu);
-                c = fmaf(w, ld_val(y, yt, base + (size_t)vv * g.cols + uu), c);
+                c = fmaf(w, ld_any(y, yt, base + (size_t)vv * g.cols + uu), c);
                 n += w;
             }
         }
     }
     if (MODE == 0) {
-        st_val(vol, vt, m, (accumulate ? ld_val(vol, vt, m) : 0.0f) + c);
+        st_any(vol, vt, m, (accumulate ? ld_any(vol, vt, m) : 0.0f) + c);
     } else if (n > 0.0f) {
-        const float w = vw ? ld_val(vw, vwt, m) : 1.0f;
-        float mu = ld_val(vol, vt, m) + lam * w * c / n;
+        const float w = vw ? ld_any(vw, vwt, m) : 1.0f;
+        float mu = ld_any(vol, vt, m) + lam * w * c / n;
         if (nonneg && mu < 0.0f) mu = 0.0f;
-        st_val(vol, vt, m, mu);
+        st_any(vol, vt, m, mu);
     }
 }
 

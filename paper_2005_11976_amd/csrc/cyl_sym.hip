@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "cyl_internal.h"
+#include "cyl_store.h"
 
 struct cyl_sym {
     const cyl_geom *geom;
@@ -45,28 +46,6 @@ struct cyl_sym {
 namespace cyl {
 
 namespace {
-
-__device__ __forceinline__ float ld_val(const void *p, int dt, size_t i) {
-    if (dt == CYL_F32) return ((const float *)p)[i];
-    if (dt == CYL_F16) return __half2float(((const __half *)p)[i]);
-    return __uint_as_float((uint32_t)((const uint16_t *)p)[i] << 16);
-}
-
-__device__ __forceinline__ void st_val(void *p, int dt, size_t i, float x) {
-    if (dt == CYL_F32) {
-        ((float *)p)[i] = x;
-    } else if (dt == CYL_F16) {
-        ((__half *)p)[i] = __float2half_rn(x);
-    } else {
-        uint32_t b = __float_as_uint(x);
-        if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x7fffffu)) {
-            ((uint16_t *)p)[i] = (uint16_t)((b >> 16) | 0x40u);
-        } else {
-            b += 0x7fffu + ((b >> 16) & 1u);
-            ((uint16_t *)p)[i] = (uint16_t)(b >> 16);
-        }
-    }
-}
 
 // Cell index with its theta index moved by s sectors (0 <= s < nt).
 __device__ __forceinline__ int32_t shifted(int32_t cell, int s, int nt, int nr) {
@@ -153,17 +132,17 @@ __global__ __launch_bounds__(256) void sym_fp_kernel(const int32_t *__restrict__
     float acc = 0.0f;
     for (int32_t i = b + lane; i < e; i += 64) {
         const int t = (int)rtheta[i] + s;
-        acc = fmaf(rlen[i], ld_val(vol, vt, (size_t)rcell[i] + (size_t)(t >= nt ? t - nt : t) * nr), acc);
+        acc = fmaf(rlen[i], ld_any(vol, vt, (size_t)rcell[i] + (size_t)(t >= nt ? t - nt : t) * nr), acc);
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if (lane != 0) return;
     const size_t o = (size_t)view * nrays + j;
     if (!SART) {
-        st_val(proj, pt, o, acc);
+        st_any(proj, pt, o, acc);
     } else {
         const float L = rowsum[j];
-        const float w = pw ? ld_val(pw, pwt, o) : 1.0f;
-        rho[j] = L > 0.0f ? w * (ld_val(proj, pt, o) - acc) / L : 0.0f;
+        const float w = pw ? ld_any(pw, pwt, o) : 1.0f;
+        rho[j] = L > 0.0f ? w * (ld_any(proj, pt, o) - acc) / L : 0.0f;
     }
 }
 
@@ -181,8 +160,8 @@ __global__ __launch_bounds__(256) void sym_update_kernel(const int32_t *__restri
     const int32_t m0 = shifted((int32_t)m, s_back, nt, nr);
     const float n = colsum[m0];
     if (!(n > 0.0f)) return;
-    const float w = vw ? ld_val(vw, vwt, m) : 1.0f;
-    const float mu0 = ld_val(vol, vt, m);
+    const float w = vw ? ld_any(vw, vwt, m) : 1.0f;
+    const float mu0 = ld_any(vol, vt, m);
     // the column's entries in order, eight loaded at a time (rays and lengths,
     // then the residual gathers) so their latencies overlap
     const int32_t b = colptr[m0], e = colptr[m0 + 1];
@@ -203,7 +182,7 @@ __global__ __launch_bounds__(256) void sym_update_kernel(const int32_t *__restri
     }
     float mu = mu0 + lam * w * c / n;
     if (nonneg && mu < 0.0f) mu = 0.0f;
-    st_val(vol, vt, m, mu);
+    st_any(vol, vt, m, mu);
 }
 
 int sym_check_launch(const char *what) {
