@@ -49,6 +49,8 @@ class Record:
     admitted: float = 0.0
     finished: float = 0.0
     latency: float = 0.0
+    status: str = "done"  # "done", "cancelled" or "failed"
+    error: str = ""
 
 
 class Resident:
@@ -63,30 +65,214 @@ class Resident:
         self.nbytes = 2 * self.prior.numel() * self.prior.element_size()
 
 
+def request_bytes(sc: I.ScanClass, itemsize):
+    """Device bytes one admitted scan of class sc holds: projection difference
+    (storage type) plus its FP32 staging, volume difference, result volume,
+    the SART workspace (the FP32 residual image and its 8x8 tile maxima) and
+    the geometry's device tables (its views, grid tables and FP dispatch
+    orders, an upper bound)."""
+    g = sc.grid
+    rows, cols, nv = sc.det_rows, sc.det_cols, sc.views.shape[0]
+    n_proj = nv * rows * cols
+    tiles = ((rows + 7) // 8) * ((cols + 7) // 8)
+    workspace = ((rows * cols + tiles) * 4 + 255) // 256 * 256
+    geometry = nv * 256 + 24 * (g.n_r + g.n_h + g.n_theta + 3) + 3 * 4 * tiles + 4096
+    return n_proj * (itemsize + 4) + 2 * g.n_vox * itemsize + workspace + geometry
+
+
+def request_rays(sc: I.ScanClass):
+    """Rays one SART step of a class-sc scan traces (one view)."""
+    return sc.det_rows * sc.det_cols
+
+
+class Scheduler:
+    """Admission and stepping of a request stream, independent of the device.
+
+    The executor does the work (`GpuExecutor` on the device; tests use a fake
+    one on the CPU):
+      now() -> seconds since the stream started; wait_until(t);
+      admit(q, t) -> handle with .total sub-iterations (may raise: the request
+        fails and frees what it took);
+      step(handles) -> one sub-iteration for each (may raise: every scan of
+        that step fails and is released, the others go on);
+      finish(handle, rec) -> result of a completed scan; release(handle);
+      drain() -> completion time of each record finished, once all work ended.
+    Admission, in arrival order: when a slot is free (max_active), the scan's
+    bytes (bytes_of(cls)) fit the budget next to the resident bytes, and the
+    rays per step of the admitted scans stay within fill_rays (one scan is
+    always admitted onto an idle executor).  A request whose bytes exceed what
+    the budget leaves on an idle executor fails at once; the queue goes on.
+    cancel: {rid: time}; a request cancelled before admission is dropped, an
+    admitted one leaves at the first step boundary at or after that time.
+    """
+
+    def __init__(self, bytes_of, rays_of, max_active=16, budget=64 << 30, resident_bytes=0,
+                 fill_rays=327680):
+        self.bytes_of, self.rays_of = bytes_of, rays_of
+        self.max_active, self.budget, self.fill_rays = max_active, budget, fill_rays
+        self.resident_bytes = resident_bytes
+        self.peak_active = 0
+
+    def run(self, requests, executor, cancel=None):
+        cancel = cancel or {}
+        pending = collections.deque(sorted(requests, key=lambda q: q.arrival))
+        active, records, results = [], [], {}
+        used, rays = self.resident_bytes, 0
+
+        def release(h):
+            nonlocal used, rays
+            used -= self.bytes_of(h.rec.cls)
+            rays -= self.rays_of(h.rec.cls)
+            executor.release(h)
+
+        while pending or active:
+            now = executor.now()
+            # drop pending requests cancelled before their admission
+            while pending and pending[0].rid in cancel and cancel[pending[0].rid] <= max(now, pending[0].arrival):
+                q = pending.popleft()
+                records.append(Record(q.rid, q.cls, q.arrival, status="cancelled"))
+            while pending and pending[0].arrival <= now and len(active) < self.max_active:
+                q = pending[0]
+                need = self.bytes_of(q.cls)
+                if used + need > self.budget:
+                    if not active:
+                        pending.popleft()
+                        records.append(Record(q.rid, q.cls, q.arrival, status="failed",
+                                              error="needs %d bytes, more than the budget leaves" % need))
+                        continue
+                    break
+                if active and rays + self.rays_of(q.cls) > self.fill_rays:
+                    break
+                pending.popleft()
+                rec = Record(q.rid, q.cls, q.arrival, admitted=now)
+                try:
+                    h = executor.admit(q, now)
+                except Exception as e:  # noqa: BLE001 - the request fails, the stream goes on
+                    rec.status, rec.error = "failed", str(e)
+                    records.append(rec)
+                    continue
+                h.rec = rec
+                used += need
+                rays += self.rays_of(q.cls)
+                active.append(h)
+            self.peak_active = max(self.peak_active, len(active))
+            if not active:
+                if pending:
+                    executor.wait_until(pending[0].arrival)
+                continue
+            try:
+                executor.step(active)
+            except Exception as e:  # noqa: BLE001 - this step's scans fail, the stream goes on
+                for h in active:
+                    h.rec.status, h.rec.error = "failed", str(e)
+                    records.append(h.rec)
+                    release(h)
+                active = []
+                continue
+            keep = []
+            now = executor.now()
+            for h in active:
+                h.cursor += 1
+                if h.cursor == h.total:
+                    results[h.rec.rid] = executor.finish(h, h.rec)
+                    records.append(h.rec)
+                    release(h)
+                elif h.rec.rid in cancel and cancel[h.rec.rid] <= now:
+                    h.rec.status = "cancelled"
+                    records.append(h.rec)
+                    release(h)
+                else:
+                    keep.append(h)
+            active = keep
+        executor.drain(records)
+        records.sort(key=lambda r: r.rid)
+        return records, results
+
+
 class _Active:
-    def __init__(self, rec, geom, dproj, delta, ws, res, n_iter, lam):
-        self.rec, self.geom, self.dproj, self.delta, self.ws = rec, geom, dproj, delta, ws
+    def __init__(self, geom, dproj, delta, ws, res, n_iter, lam):
+        self.geom, self.dproj, self.delta, self.ws = geom, dproj, delta, ws
         self.res, self.cursor, self.lam = res, 0, lam
         self.total = n_iter * geom.scan.n_views
+        self.rec = None
 
     def entry(self):
         return cyl.BatchEntry(self.geom, self.cursor % self.geom.scan.n_views, self.dproj, self.delta,
                               self.ws, vox_weights=self.res.weights, lam=self.lam)
 
 
-def request_bytes(sc: I.ScanClass, itemsize):
-    """Device bytes one admitted scan of class sc holds: projection difference
-    (storage type) plus its FP32 staging, volume difference, result volume and
-    the FP32 residual image."""
-    g = sc.grid
-    n_proj = sc.views.shape[0] * sc.det_rows * sc.det_cols
-    return (n_proj * (itemsize + 4) + 2 * g.n_vox * itemsize
-            + ((sc.det_rows * sc.det_cols * 4 + 255) // 256) * 256)
+class GpuExecutor:
+    """Runs admitted scans on one GPU stream: one cyl_sart_batch_step per step
+    (two kernel launches for up to 16 scans), at most two steps queued ahead of
+    the GPU; times from CUDA events on that stream."""
 
+    def __init__(self, residents, data, n_iter, lam, device, stream):
+        import torch
+        self.res, self.data, self.n_iter, self.lam = residents, data, n_iter, lam
+        self.device, self.stream = device, stream
+        self.dtype = residents[0].prior.dtype
+        self.start = torch.cuda.Event(enable_timing=True)
+        self.start.record(stream)
+        self.t0 = time.perf_counter()
+        self.inflight = collections.deque()
+        self.retired = []   # geometries of released scans, destroyed once their last step is done
+        self.done = {}      # rid -> completion event
 
-def request_rays(sc: I.ScanClass):
-    """Rays one SART step of a class-sc scan traces (one view)."""
-    return sc.det_rows * sc.det_cols
+    def now(self):
+        return time.perf_counter() - self.t0
+
+    def wait_until(self, t):
+        wait = t - self.now()
+        if wait > 0:
+            time.sleep(wait)
+
+    def admit(self, q, now):
+        import torch
+        r = self.res[q.cls]
+        geom = cyl.Geometry(r.sc.scan(q.R, q.T), self.device)
+        dev = "cuda:%d" % self.device
+        p32 = torch.empty(geom.scan.proj_shape, dtype=torch.float32, device=dev)
+        p32.copy_(self.data[q.rid], non_blocking=True)
+        dproj = geom.fp_diff(r.prior, p32, out_dtype=self.dtype, stream=self.stream)
+        del p32  # stream-ordered: its memory is reused only by later work on this stream
+        delta = torch.zeros_like(r.prior)
+        ws = torch.empty(geom.workspace_bytes(), dtype=torch.uint8, device=dev)
+        return _Active(geom, dproj, delta, ws, r, self.n_iter, self.lam)
+
+    def step(self, handles):
+        import torch
+        cyl.sart_batch_step([h.entry() for h in handles], self.stream)
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(self.stream)
+        self.inflight.append(ev)
+        if len(self.inflight) > 2:
+            self.inflight.popleft().synchronize()
+        while self.retired and self.retired[0][1].query():
+            self.retired.pop(0)[0].close()
+
+    def finish(self, h, rec):
+        import torch
+        vol = cyl.add(h.res.prior, h.delta, stream=self.stream)
+        done = torch.cuda.Event(enable_timing=True)
+        done.record(self.stream)
+        self.done[rec.rid] = done
+        return vol
+
+    def release(self, h):
+        import torch
+        ev = torch.cuda.Event()
+        ev.record(self.stream)
+        self.retired.append((h.geom, ev))
+
+    def drain(self, records):
+        self.stream.synchronize()
+        for g, _ in self.retired:
+            g.close()
+        self.retired = []
+        for rec in records:
+            if rec.rid in self.done:
+                rec.finished = self.start.elapsed_time(self.done[rec.rid]) * 1e-3
+                rec.latency = rec.finished - rec.arrival
 
 
 class Server:
@@ -110,92 +296,26 @@ class Server:
         self.resident_bytes = sum(r.nbytes for r in residents)
         if self.resident_bytes > hbm_budget:
             raise ValueError("resident class data exceeds the HBM budget")
+        self.peak_active = 0
 
-    def run(self, requests, data):
+    def run(self, requests, data, cancel=None):
         """Serve `requests` (inputs.Request, arrival seconds from now) whose
-        projections are data[rid] (pinned host tensors in the storage dtype).
-        Returns (records, volumes): per-request timing and result volumes."""
+        projections are data[rid] (pinned host tensors, FP32).  Returns
+        (records, volumes): per-request timing and status, and the result
+        volume of every scan that completed."""
         import torch
         itemsize = torch.empty((), dtype=self.dtype).element_size()
-        pending = collections.deque(sorted(requests, key=lambda q: q.arrival))
-        active, finished, volumes = [], [], {}
-        retired = []  # geometries of finished scans, destroyed once their last step is done
-        used = self.resident_bytes
-        rays = 0
-        inflight = collections.deque()
-        start = torch.cuda.Event(enable_timing=True)
+        sched = Scheduler(lambda c: request_bytes(self.res[c].sc, itemsize),
+                          lambda c: request_rays(self.res[c].sc), self.max_active, self.budget,
+                          self.resident_bytes, self.fill_rays)
         with torch.cuda.stream(self.stream):
-            start.record(self.stream)
-            t0 = time.perf_counter()
-            while pending or active:
-                now = time.perf_counter() - t0
-                while pending and pending[0].arrival <= now and len(active) < self.max_active:
-                    q = pending[0]
-                    sc = self.res[q.cls].sc
-                    need = request_bytes(sc, itemsize)
-                    if used + need > self.budget:
-                        if not active:
-                            raise ValueError("request %d needs %d bytes, more than the HBM budget "
-                                             "leaves" % (q.rid, need))
-                        break
-                    if active and rays + request_rays(sc) > self.fill_rays:
-                        break
-                    pending.popleft()
-                    used += need
-                    rays += request_rays(sc)
-                    active.append(self._admit(q, data[q.rid], now))
-                if not active:
-                    wait = pending[0].arrival - (time.perf_counter() - t0)
-                    if wait > 0:
-                        time.sleep(wait)
-                    continue
-                cyl.sart_batch_step([a.entry() for a in active], self.stream)
-                ev = torch.cuda.Event(enable_timing=True)
-                ev.record(self.stream)
-                keep = []
-                for a in active:
-                    a.cursor += 1
-                    if a.cursor == a.total:
-                        volumes[a.rec.rid] = cyl.add(a.res.prior, a.delta, stream=self.stream)
-                        done = torch.cuda.Event(enable_timing=True)
-                        done.record(self.stream)
-                        finished.append((a.rec, done))
-                        used -= request_bytes(a.res.sc, itemsize)
-                        rays -= request_rays(a.res.sc)
-                        retired.append((a.geom, done))
-                    else:
-                        keep.append(a)
-                active = keep
-                # keep at most two steps queued ahead of the GPU
-                inflight.append(ev)
-                if len(inflight) > 2:
-                    inflight.popleft().synchronize()
-                while retired and retired[0][1].query():
-                    retired.pop(0)[0].close()
-            self.stream.synchronize()
-            for g, _ in retired:
-                g.close()
-        records = []
-        for rec, ev in finished:
-            rec.finished = start.elapsed_time(ev) * 1e-3
-            rec.latency = rec.finished - rec.arrival
-            records.append(rec)
-        records.sort(key=lambda r: r.rid)
+            ex = GpuExecutor(self.res, data, self.n_iter, self.lam, self.device, self.stream)
+            records, volumes = sched.run(requests, ex, cancel)
+        self.peak_active = sched.peak_active
+        for rec in records:
+            if rec.status == "failed" and "budget" in rec.error:
+                raise ValueError("request %d %s" % (rec.rid, rec.error))
         return records, volumes
-
-    def _admit(self, q, host_proj, now):
-        import torch
-        r = self.res[q.cls]
-        geom = cyl.Geometry(r.sc.scan(q.R, q.T), self.device)
-        dev = "cuda:%d" % self.device
-        p32 = torch.empty(geom.scan.proj_shape, dtype=torch.float32, device=dev)
-        p32.copy_(host_proj, non_blocking=True)
-        dproj = geom.fp_diff(r.prior, p32, out_dtype=self.dtype, stream=self.stream)
-        del p32  # stream-ordered: its memory is reused only by later work on this stream
-        delta = torch.zeros_like(r.prior)
-        ws = torch.empty(geom.workspace_bytes(), dtype=torch.uint8, device=dev)
-        return _Active(Record(q.rid, q.cls, q.arrival, admitted=now), geom, dproj, delta, ws, r,
-                       self.n_iter, self.lam)
 
 
 def run_fifo(residents, requests, data, n_iter=15, lam=0.5, device=0, stream=None):

@@ -39,8 +39,9 @@ def test_served_equals_alone_and_fifo(setup):
     say("serve mixed", len(reqs), "requests")
     srv = serve.Server(res16, n_iter=n_iter, max_active=4)
     recs, vols = srv.run(reqs, data)
-    assert len(recs) == len(reqs) and all(r.latency > 0 for r in recs)
-    say("serve", serve.latency_summary(recs))
+    assert len(recs) == len(reqs) and all(r.latency > 0 and r.status == "done" for r in recs)
+    say("serve", serve.latency_summary(recs), "peak active scans", srv.peak_active)
+    assert srv.peak_active > 1  # the burst of arrivals shares steps
     say("fifo fp32")
     frecs, fvols = serve.run_fifo(res32, reqs, data, n_iter=n_iter)
     for q in reqs:
@@ -61,6 +62,7 @@ def test_budget_limits_admission(setup):
     srv = serve.Server(res16, n_iter=1, max_active=16, hbm_budget=srv_res_bytes(res16) + one)
     say("serve with a budget of one scan")
     recs, vols = srv.run(reqs, data)
+    assert srv.peak_active == 1
     ref = serve.Server(res16, n_iter=1, max_active=16)
     recs2, vols2 = ref.run(reqs, data)
     for q in reqs:
