@@ -341,6 +341,24 @@ int cyl_side_sums(int32_t n_views, int32_t rows, int32_t cols, const void *proj,
  * non-finite values. */
 int cyl_azimuth_phase(int32_t n, const double *s, const double *s_ref, double *alpha);
 
+/* Sec. 2.1, Eq. 5: the object's last Euler angle from the perceived phase
+ * phi_p of the grey-value signal, the geometric angle phi_g of the scanner's
+ * optical axis and the first two Euler angles a1, a2 of Eq. 1 (the paper's
+ * alpha and beta): gamma = phi_p - phi_g - arctan(tan(a1) / cos(a2)), the
+ * arctangent taken as atan2(sin a1, cos a1 cos a2) so that it stays continuous
+ * through a1 = +-pi/2; gamma is wrapped to [0, 2 pi).  Host call.  CYL_EINVAL
+ * for a NULL output, non-finite arguments or cos(a2) = 0. */
+int cyl_gamma_from_phase(double phi_p, double phi_g, double a1, double a2, double *gamma);
+
+/* The two points of the projected symmetry axis per view from the output of
+ * cyl_axis_corners (Sec. 2.1): top = centre of the top-left and top-right
+ * corners, bottom = centre of the bottom-left and bottom-right ones, as
+ * (u, v) pixel coordinates; valid[k] = 1 where view k has pixels above the
+ * threshold, else 0 (and its points are -1).  Host call on host arrays:
+ * corners [n_views][9] (int32, as written by cyl_axis_corners), top and bottom
+ * [n_views][2], valid [n_views].  CYL_EINVAL for n_views < 1 or NULL arrays. */
+int cyl_axis_points(int32_t n_views, const int32_t *corners, double *top, double *bottom, uint8_t *valid);
+
 /* The paper's own projector pair (Sec. 2.2), for comparison with the exact
  * pair above.  Forward projection, pixel driven: each ray (source -> pixel
  * centre) is sampled at distances (k + 1/2) step from the source; each sample

@@ -21,6 +21,8 @@ point = centre of the two bottom corners.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 
@@ -175,3 +177,13 @@ def azimuth_phase(s, s_ref):
             break
         t -= d1 / d2
     return float(np.mod(t, 2 * np.pi))
+
+
+def gamma_eq5(phi_p, phi_g, a1, a2):
+    """Sec. 2.1, Eq. 5: the last Euler angle from the perceived phase phi_p,
+    the geometric angle phi_g and the first two Euler angles a1, a2:
+    phi_p - phi_g - arctan(tan(a1) / cos(a2)), the arctangent continued
+    through a1 = +-pi/2 (atan2(sin a1, cos a1 cos a2)), wrapped to [0, 2 pi)."""
+    corr = math.atan2(math.sin(a1), math.cos(a1) * math.cos(a2))
+    g = phi_p - phi_g - corr
+    return g - 2.0 * math.pi * math.floor(g / (2.0 * math.pi))

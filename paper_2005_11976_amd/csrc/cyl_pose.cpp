@@ -272,3 +272,35 @@ extern "C" int cyl_azimuth_phase(int32_t n, const double *s, const double *s_ref
     *alpha = t;
     return CYL_OK;
 }
+
+extern "C" int cyl_gamma_from_phase(double phi_p, double phi_g, double a1, double a2, double *gamma) {
+    if (!gamma || !std::isfinite(phi_p) || !std::isfinite(phi_g) || !std::isfinite(a1) || !std::isfinite(a2) ||
+        std::cos(a2) == 0.0) {
+        set_error("cyl_gamma_from_phase: NULL output, non-finite angle or cos(a2) = 0");
+        return CYL_EINVAL;
+    }
+    // Eq. 5, the arctangent of tan(a1) / cos(a2) as a continuous atan2
+    const double corr = std::atan2(std::sin(a1), std::cos(a1) * std::cos(a2));
+    double g = phi_p - phi_g - corr;
+    g -= 2.0 * M_PI * std::floor(g / (2.0 * M_PI));
+    *gamma = g >= 2.0 * M_PI ? 0.0 : g;
+    return CYL_OK;
+}
+
+extern "C" int cyl_axis_points(int32_t n_views, const int32_t *corners, double *top, double *bottom,
+                               uint8_t *valid) {
+    if (n_views < 1 || !corners || !top || !bottom || !valid) {
+        set_error("cyl_axis_points: n_views < 1 or NULL array");
+        return CYL_EINVAL;
+    }
+    for (int k = 0; k < n_views; ++k) {
+        const int32_t *c = corners + 9 * (size_t)k;
+        const bool ok = c[8] > 0;
+        valid[k] = ok ? 1 : 0;
+        for (int i = 0; i < 2; ++i) {
+            top[2 * k + i] = ok ? 0.5 * ((double)c[i] + (double)c[2 + i]) : -1.0;
+            bottom[2 * k + i] = ok ? 0.5 * ((double)c[4 + i] + (double)c[6 + i]) : -1.0;
+        }
+    }
+    return CYL_OK;
+}

@@ -22,7 +22,7 @@ EXPORTS = ["cyl_geom_create", "cyl_geom_destroy", "cyl_fp", "cyl_bp", "cyl_row_s
            "cyl_sart_workspace_bytes", "cyl_sart_run", "cyl_sart_run_static", "cyl_os_sart_workspace_bytes", "cyl_os_sart_run",
            "cyl_sart_residual", "cyl_sart_update",
            "cyl_sart_batch_step", "cyl_fp_diff", "cyl_add", "cyl_axis_corners", "cyl_track_point",
-           "cyl_pose_from_axis", "cyl_side_sums", "cyl_azimuth_phase", "cyl_mtf", "cyl_fp_sampled", "cyl_bp_voxel", "cyl_sart_run_sampled", "cyl_sym_create", "cyl_sym_destroy", "cyl_sym_nnz",
+           "cyl_pose_from_axis", "cyl_side_sums", "cyl_azimuth_phase", "cyl_gamma_from_phase", "cyl_axis_points", "cyl_mtf", "cyl_fp_sampled", "cyl_bp_voxel", "cyl_sart_run_sampled", "cyl_sym_create", "cyl_sym_destroy", "cyl_sym_nnz",
            "cyl_sym_fp", "cyl_sym_sart_run", "cyl_last_error", "cyl_version"]
 
 
@@ -113,6 +113,10 @@ def declare(lib):
     lib.cyl_side_sums.restype = C.c_int
     lib.cyl_azimuth_phase.argtypes = [i32, P(C.c_double), P(C.c_double), P(C.c_double)]
     lib.cyl_azimuth_phase.restype = C.c_int
+    lib.cyl_gamma_from_phase.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, P(C.c_double)]
+    lib.cyl_gamma_from_phase.restype = C.c_int
+    lib.cyl_axis_points.argtypes = [i32, P(C.c_int32), P(C.c_double), P(C.c_double), P(C.c_uint8)]
+    lib.cyl_axis_points.restype = C.c_int
     lib.cyl_mtf.argtypes = [i32, i32, i32, vp, C.c_int, i32, vp, i32, vp]
     lib.cyl_mtf.restype = C.c_int
     lib.cyl_fp_sampled.argtypes = [vp, vp, C.c_int, vp, C.c_int, i32, i32, C.c_double, i32, vp]
@@ -533,14 +537,28 @@ def axis_corners(proj, threshold, dilate=1, stream=None, _lib=None):
     return out
 
 
-def axis_points(corners):
-    """Top and bottom axis points (u, v) per view from cyl_axis_corners output
-    (host arrays [n, 2] each, and the mask of views with a segment)."""
-    c = np.asarray(corners, dtype=np.float64)
-    valid = c[:, 8] > 0
-    top = 0.5 * (c[:, 0:2] + c[:, 2:4])
-    bottom = 0.5 * (c[:, 4:6] + c[:, 6:8])
-    return top, bottom, valid
+def axis_points(corners, _lib=None):
+    """cyl_axis_points (host): top and bottom axis points (u, v) per view from
+    cyl_axis_corners output ([n, 9] int32), and the mask of views with a
+    segment."""
+    L = _lib or lib()
+    c = np.ascontiguousarray(np.asarray(corners), dtype=np.int32)
+    n = c.shape[0]
+    top = np.zeros((n, 2))
+    bottom = np.zeros((n, 2))
+    valid = np.zeros(n, dtype=np.uint8)
+    _check(L.cyl_axis_points(n, c.ctypes.data_as(C.POINTER(C.c_int32)), top.ctypes.data_as(C.POINTER(C.c_double)),
+                             bottom.ctypes.data_as(C.POINTER(C.c_double)), valid.ctypes.data_as(C.POINTER(C.c_uint8))),
+           L)
+    return top, bottom, valid.astype(bool)
+
+
+def gamma_from_phase(phi_p, phi_g, a1, a2, _lib=None):
+    """cyl_gamma_from_phase (host): the last Euler angle of Eq. 5."""
+    L = _lib or lib()
+    out = C.c_double()
+    _check(L.cyl_gamma_from_phase(float(phi_p), float(phi_g), float(a1), float(a2), C.byref(out)), L)
+    return out.value
 
 
 def track_point(views, rows, cols, uv, valid=None, _lib=None):
