@@ -95,9 +95,12 @@ def serving(args):
     torch.cuda.synchronize()
     srv = serve.Server(res16, n_iter=args.serve_iters, max_active=16, hbm_budget=64 << 30)
     log("serving: batched run")
-    recs, vols = srv.run(reqs, data)
+    def prog(n):
+        if n % 16 == 0:
+            log("serving: %d of %d requests done" % (n, len(reqs)))
+    recs, vols = srv.run(reqs, data, progress=prog)
     log("serving: per-scan FP32 run")
-    frecs, fvols = serve.run_fifo(res32, reqs, data, n_iter=args.serve_iters)
+    frecs, fvols = serve.run_fifo(res32, reqs, data, n_iter=args.serve_iters, progress=prog)
     errs = [float((vols[q.rid].float() - fvols[q.rid]).norm() / fvols[q.rid].norm()) for q in reqs]
     b, f = serve.latency_summary(recs), serve.latency_summary(frecs)
     log("serving: batched p50 %.2f s p99 %.2f s %.3f scans/s; fifo p50 %.2f s p99 %.2f s %.3f scans/s"

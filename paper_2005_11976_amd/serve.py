@@ -113,7 +113,9 @@ class Scheduler:
         self.resident_bytes = resident_bytes
         self.peak_active = 0
 
-    def run(self, requests, executor, cancel=None):
+    def run(self, requests, executor, cancel=None, progress=None):
+        """progress(n): called with the number of records so far after each
+        step that completes, cancels or fails a scan."""
         cancel = cancel or {}
         pending = collections.deque(sorted(requests, key=lambda q: q.arrival))
         active, records, results = [], [], {}
@@ -183,6 +185,8 @@ class Scheduler:
                     release(h)
                 else:
                     keep.append(h)
+            if progress and len(keep) < len(active):
+                progress(len(records))
             active = keep
         executor.drain(records)
         records.sort(key=lambda r: r.rid)
@@ -298,11 +302,11 @@ class Server:
             raise ValueError("resident class data exceeds the HBM budget")
         self.peak_active = 0
 
-    def run(self, requests, data, cancel=None):
+    def run(self, requests, data, cancel=None, progress=None):
         """Serve `requests` (inputs.Request, arrival seconds from now) whose
         projections are data[rid] (pinned host tensors, FP32).  Returns
         (records, volumes): per-request timing and status, and the result
-        volume of every scan that completed."""
+        volume of every scan that completed.  progress: see Scheduler.run."""
         import torch
         itemsize = torch.empty((), dtype=self.dtype).element_size()
         sched = Scheduler(lambda c: request_bytes(self.res[c].sc, itemsize),
@@ -310,7 +314,7 @@ class Server:
                           self.resident_bytes, self.fill_rays)
         with torch.cuda.stream(self.stream):
             ex = GpuExecutor(self.res, data, self.n_iter, self.lam, self.device, self.stream)
-            records, volumes = sched.run(requests, ex, cancel)
+            records, volumes = sched.run(requests, ex, cancel, progress)
         self.peak_active = sched.peak_active
         for rec in records:
             if rec.status == "failed" and "budget" in rec.error:
@@ -318,7 +322,7 @@ class Server:
         return records, volumes
 
 
-def run_fifo(residents, requests, data, n_iter=15, lam=0.5, device=0, stream=None):
+def run_fifo(residents, requests, data, n_iter=15, lam=0.5, device=0, stream=None, progress=None):
     """The plain per-scan loop: requests in arrival order, one cyl_sart_run
     each on its own (no batching), queued on one stream as they arrive; same
     timing rules as Server.run."""
@@ -344,6 +348,8 @@ def run_fifo(residents, requests, data, n_iter=15, lam=0.5, device=0, stream=Non
             ev.record(stream)
             finished.append((Record(q.rid, q.cls, q.arrival), ev))
             volumes[q.rid] = vol
+            if progress:
+                progress(len(finished))
         stream.synchronize()
     for g in geoms:
         g.close()
