@@ -108,7 +108,9 @@ def serving(args):
     return {"requests": len(reqs), "rate_per_s": args.serve_rate, "iterations": args.serve_iters,
             "classes": "".join(classes[c].name for c in used),
             "dtype": "f16 storage (prior + difference form), f32 arithmetic",
-            "hbm_budget_gb": 64, "slots": 16, "fill_rays": srv.fill_rays, "batched": b, "per_scan_fp32": f,
+            "hbm_budget_gb": 64, "slots": 16, "fill_rays": srv.fill_rays, "bypass": srv.bypass,
+            "bypassed_admissions": srv.bypassed, "peak_active_scans": srv.peak_active,
+            "batched": b, "per_scan_fp32": f,
             "throughput_ratio": b["scans_per_s"] / f["scans_per_s"],
             "p99_ratio": b["p99_s"] / f["p99_s"],
             "rel_err_vs_per_scan_fp32": {"max": max(errs), "mean": float(np.mean(errs))}}

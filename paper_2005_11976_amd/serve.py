@@ -104,14 +104,20 @@ class Scheduler:
     the budget leaves on an idle executor fails at once; the queue goes on.
     cancel: {rid: time}; a request cancelled before admission is dropped, an
     admitted one leaves at the first step boundary at or after that time.
+    bypass: while the head of the queue waits only for ray capacity (a large
+    scan behind running ones), up to this many later arrivals that fit are
+    admitted past it, so that the GPU keeps work to overlap; then the head is
+    waited for.
     """
 
     def __init__(self, bytes_of, rays_of, max_active=16, budget=64 << 30, resident_bytes=0,
-                 fill_rays=327680):
+                 fill_rays=327680, bypass=0):
         self.bytes_of, self.rays_of = bytes_of, rays_of
         self.max_active, self.budget, self.fill_rays = max_active, budget, fill_rays
         self.resident_bytes = resident_bytes
+        self.bypass = bypass
         self.peak_active = 0
+        self.bypassed = 0
 
     def run(self, requests, executor, cancel=None, progress=None):
         """progress(n): called with the number of records so far after each
@@ -120,6 +126,7 @@ class Scheduler:
         pending = collections.deque(sorted(requests, key=lambda q: q.arrival))
         active, records, results = [], [], {}
         used, rays = self.resident_bytes, 0
+        head_rid, head_passed = None, 0
 
         def release(h):
             nonlocal used, rays
@@ -144,8 +151,31 @@ class Scheduler:
                         continue
                     break
                 if active and rays + self.rays_of(q.cls) > self.fill_rays:
-                    break
-                pending.popleft()
+                    # the head waits for ray capacity only: admit a later arrival that fits
+                    if head_rid != q.rid:
+                        head_rid, head_passed = q.rid, 0
+                    if head_passed >= self.bypass:
+                        break
+                    pick = None
+                    for i in range(1, len(pending)):
+                        q2 = pending[i]
+                        if q2.arrival > now:
+                            break
+                        if q2.rid in cancel and cancel[q2.rid] <= now:
+                            continue
+                        if (used + self.bytes_of(q2.cls) <= self.budget
+                                and rays + self.rays_of(q2.cls) <= self.fill_rays):
+                            pick = i
+                            break
+                    if pick is None:
+                        break
+                    q = pending[pick]
+                    del pending[pick]
+                    need = self.bytes_of(q.cls)
+                    head_passed += 1
+                    self.bypassed += 1
+                else:
+                    pending.popleft()
                 rec = Record(q.rid, q.cls, q.arrival, admitted=now)
                 try:
                     h = executor.admit(q, now)
@@ -289,8 +319,9 @@ class Server:
     """
 
     def __init__(self, residents, n_iter=15, lam=0.5, max_active=16, hbm_budget=64 << 30,
-                 fill_rays=327680, device=0, stream=None):
+                 fill_rays=327680, device=0, stream=None, bypass=4):
         import torch
+        self.bypass = bypass
         self.res = residents
         self.n_iter, self.lam = n_iter, lam
         self.max_active, self.budget, self.fill_rays = max_active, hbm_budget, fill_rays
@@ -311,11 +342,12 @@ class Server:
         itemsize = torch.empty((), dtype=self.dtype).element_size()
         sched = Scheduler(lambda c: request_bytes(self.res[c].sc, itemsize),
                           lambda c: request_rays(self.res[c].sc), self.max_active, self.budget,
-                          self.resident_bytes, self.fill_rays)
+                          self.resident_bytes, self.fill_rays, self.bypass)
         with torch.cuda.stream(self.stream):
             ex = GpuExecutor(self.res, data, self.n_iter, self.lam, self.device, self.stream)
             records, volumes = sched.run(requests, ex, cancel, progress)
         self.peak_active = sched.peak_active
+        self.bypassed = sched.bypassed
         for rec in records:
             if rec.status == "failed" and "budget" in rec.error:
                 raise ValueError("request %d %s" % (rec.rid, rec.error))

@@ -143,3 +143,21 @@ def test_oversized_request_fails_and_queue_goes_on():
     recs, res = sched(budget=30).run(reqs, ex)
     assert recs[0].status == "failed" and "budget" in recs[0].error
     assert recs[1].status == "done" and set(res) == {1}
+
+
+def test_bounded_bypass_of_a_head_waiting_for_rays():
+    # a class-1 scan runs (6 of 10 rays); the next class-1 scan waits for rays,
+    # and up to `bypass` class-0 scans behind it (2 rays each) run meanwhile
+    reqs = [Req(0, 1, 0.0), Req(1, 1, 0.0)] + [Req(2 + i, 0, 0.0) for i in range(5)]
+    ex = FakeExecutor(steps_of=(1, 4))
+    s = Scheduler(lambda c: (10, 40)[c], lambda c: (2, 6)[c], 8, 1000, 0, 10, bypass=2)
+    recs, _ = s.run(reqs, ex)
+    assert all(r.status == "done" for r in recs)
+    admits = [e[1] for e in ex.log if e[0] == "admit"]
+    assert admits[:3] == [0, 2, 3]        # two class-0 scans pass the waiting class-1 scan
+    assert admits[3] == 1                 # then the head is waited for
+    assert s.bypassed == 2
+    ex0 = FakeExecutor(steps_of=(1, 4))
+    s0 = Scheduler(lambda c: (10, 40)[c], lambda c: (2, 6)[c], 8, 1000, 0, 10, bypass=0)
+    s0.run(reqs, ex0)
+    assert [e[1] for e in ex0.log if e[0] == "admit"][:2] == [0, 1]   # strict arrival order
