@@ -156,3 +156,49 @@ def test_internal_rotation_chain(torch_cuda):
     say("internal rotation: %.4f rad (reference chain %.4f), error %.3f deg" % (a, b, err))
     assert abs(a - b) < 1e-6
     assert abs(err) < 1.5
+
+
+def test_pose_and_internal_rotation_from_projections_only(torch_cuda):
+    """The whole chain of Sec. 2.1 from the measured projections alone, the
+    truth used only to score the result: corner pixels (cyl_axis_corners),
+    axis points (cyl_axis_points), two tracked 3-D axis points
+    (cyl_track_point), the axis pose with no internal rotation
+    (cyl_pose_from_axis, the cap heights from the part's design), reference
+    projections of the part under that pose, side sums of both beside the
+    tracked axis (cyl_side_sums) and the internal rotation
+    (cyl_azimuth_phase).  A tilted, shifted part with two off-axis
+    inclusions."""
+    from paper_2005_11976_amd import cyl
+    g = I.Grid(24, 96, 16, 0.0, 25.0, -25.0, 25.0)
+    dh = (g.h_max - g.h_min) / g.n_h
+    vol = np.zeros(g.shape, np.float32)
+    vol[2:22, :, :14] = 0.01
+    vol[6:18, 8:20, 9:13] = 0.03
+    vol[4:9, 50:58, 5:8] = 0.025
+    h_bot, h_top = g.h_min + 2 * dh, g.h_min + 22 * dh
+    views = I.circular_views(90, 200.0, 400.0, 0.8)
+    alpha_true = 2.1
+    R, T = I.pose_from(alpha_true, math.radians(3.0), 1.2, [0.9, -0.6, 0.4])
+    meas = cyl.Geometry(I.Scan(g, views, 128, 128, R, T), 0)
+    say("closed chain: measured projections")
+    p = meas.fp(dev(vol))
+    corners = host(cyl.axis_corners(p, float(np.float32(0.02)), 1))
+    top_uv, bot_uv, valid = cyl.axis_points(corners)
+    assert valid.sum() >= 80
+    lo, _ = cyl.track_point(views, 128, 128, top_uv, valid)
+    hi_, _ = cyl.track_point(views, 128, 128, bot_uv, valid)
+    R0, T0 = cyl.pose_from_axis(hi_, lo, h_top, h_bot, 0.0)
+    d_true, d0 = R.T @ np.array([0.0, 0.0, 1.0]), R0.T @ np.array([0.0, 0.0, 1.0])
+    ang = math.degrees(math.acos(min(1.0, float(d0 @ d_true))))
+    # the axis in each view, from the tracked pose only
+    ax = P.project(views, 128, 128, -R0.T @ T0)[:, 0]
+    ss_m = host(cyl.side_sums(p, ax, np.zeros(90), np.full(90, 127)))
+    say("closed chain: reference projections under the tracked pose")
+    ref = cyl.Geometry(I.Scan(g, views, 128, 128, R0, T0), 0)
+    pr = ref.fp(dev(vol))
+    ss_r = host(cyl.side_sums(pr, ax, np.zeros(90), np.full(90, 127)))
+    a = cyl.azimuth_phase(ss_m[:, 1] - ss_m[:, 0], ss_r[:, 1] - ss_r[:, 0])
+    err = math.degrees((a - alpha_true + math.pi) % (2 * math.pi) - math.pi)
+    say("closed chain: axis error %.3f deg, internal rotation %.4f rad, error %.3f deg" % (ang, a, err))
+    assert ang < 0.5
+    assert abs(err) < 2.0
